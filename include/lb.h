@@ -1,0 +1,183 @@
+/*
+ * lb.h -- C ABI of the thread-safe regularized lattice Boltzmann library
+ * (liblb.so) for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Montessori et al., "Thread-safe lattice Boltzmann for
+ * high-performance computing on GPUs".  One time step is
+ *   (1) moments: rho, j = rho u, Pi^neq of every node from its populations
+ *       (Section 4, moment snippet; Section 2, moment definitions);
+ *   (2) fused streaming + collision: every population of every node is
+ *       rebuilt from the moments of the node it streams from, by Hermite
+ *       projection of the non-equilibrium part (Section 3, eq. LBexp, eq.
+ *       pushLB, eq. hermite and the full stream-and-collide equation);
+ *   (3) boundary conditions (Section 4), fused into (2).
+ * Only one population set per species is allocated; the sweep (2) never
+ * reads populations, so it updates them in place without races.
+ *
+ * Conventions
+ *   - All entry points return an lb_status (0 = LB_OK, negative on error)
+ *     unless stated otherwise.  No C++ exception crosses this interface.
+ *   - Host arrays are FP64, structure-of-arrays, node index
+ *     n = x + nx*(y + ny*z), x fastest.  D = 2 for D2Q9, 3 otherwise.
+ *   - Velocity u has D*N entries (all x, then all y, then all z).
+ *   - The non-equilibrium stress Pi^neq has D(D+1)/2 * N entries, ordered
+ *     xx, yy, (zz), xy, (xz, yz).
+ *   - A handle is not safe for concurrent calls from several threads;
+ *     distinct handles may be used from different threads.
+ *   - Population storage order on the device is internal; the ABI exposes
+ *     moments only.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,       /* invalid argument or parameter combination */
+  LB_ENOMEM = -2,       /* device or host allocation failed / buffer too small */
+  LB_EUNSUPPORTED = -3, /* valid request this build does not implement */
+  LB_EDEVICE = -4,      /* HIP runtime error (launch, copy, synchronisation) */
+  LB_ENONFINITE = -5    /* non-finite value in input or in the evolved state */
+};
+
+/* Velocity sets (Section 2: "q depending on the dimensionality and isotropy
+ * of the lattice"); textbook weights, cs^2 = 1/3. */
+enum lb_lattice { LB_D2Q9 = 9, LB_D3Q19 = 19, LB_D3Q27 = 27 };
+
+/* Boundary condition of one axis, applied at both ends of the axis.
+ * LB_BOUNCEBACK is halfway bounce-back: the wall sits half a lattice spacing
+ * beyond the first and last node layer (Section 5.1 uses bounce-back walls). */
+enum lb_boundary { LB_PERIODIC = 0, LB_BOUNCEBACK = 1 };
+
+/* Population storage precision.  The *_S modes store f_a - t_a*rho0 (the
+ * deviation from the rest state) in 16 bits with round-to-nearest-even; the
+ * paper proposes half-precision population storage with single-precision
+ * arithmetic as future work (Sections 6.1, 6.3, 7). */
+enum lb_storage {
+  LB_STORE_F64 = 0,   /* requires LB_COMPUTE_F64 */
+  LB_STORE_F32 = 1,
+  LB_STORE_F16S = 2,
+  LB_STORE_BF16S = 3
+};
+
+/* Arithmetic precision of the kernels.  LB_COMPUTE_F64 requires
+ * LB_STORE_F64; the 32-bit-compute modes keep their moments in FP32. */
+enum lb_compute { LB_COMPUTE_F64 = 0, LB_COMPUTE_F32 = 1 };
+
+/* Problem statement (Sections 2-3).  Fill with lb_params_default first;
+ * struct_size must be sizeof(lb_params) so the layout can grow. */
+typedef struct lb_params {
+  size_t struct_size;     /* = sizeof(lb_params) */
+  int32_t lattice;        /* enum lb_lattice */
+  int32_t hermite_order;  /* 2, or 3 (D3Q27 only): order of the Hermite
+                             expansion of equilibrium and non-equilibrium
+                             (eq. hermite, truncated at n = 2 in the paper) */
+  int64_t nx, ny, nz;     /* lattice nodes per axis; nz = 1 for D2Q9 */
+  int32_t bc[3];          /* enum lb_boundary per axis x, y, z */
+  int32_t species;        /* 1, or 2 for the colour-gradient model (Sec. 2.1) */
+  double tau;             /* relaxation time, omega = 1/tau; tau > 1/2 */
+  double rho0;            /* bulk density of the incompressible equilibrium
+                             (eq. equil); > 0 */
+  double force[3];        /* constant body-force density (Section 2 "forcing
+                             terms"; scheme not given there): Guo's source
+                             term, so each node's momentum gains F per step
+                             and u = (j + F/2)/rho0 */
+  double sigma;           /* colour-gradient surface tension (species = 2) */
+  double beta;            /* recolouring parameter (species = 2), 0..1 */
+  int32_t storage;        /* enum lb_storage */
+  int32_t compute;        /* enum lb_compute */
+} lb_params;
+
+typedef struct lb_handle lb_handle;
+
+/* Fill *p with a valid default problem (D3Q19, 32^3, periodic, tau 0.6,
+ * rho0 1, no force, one species, FP32 storage and compute).  p != NULL. */
+void lb_params_default(lb_params* p);
+
+/* Exact number of device bytes lb_create needs for these parameters:
+ * populations (species * Q arrays) + moments (M arrays) + reduction scratch,
+ * each array padded to a 256-byte boundary (Section 4 counts 15 arrays for
+ * D2Q9 and 29 for D3Q19 in single precision).  Returns 0 for invalid
+ * parameters. */
+size_t lb_required_bytes(const lb_params* p);
+
+/* Validate parameters without touching the device. */
+int lb_validate(const lb_params* p);
+
+/* Create a simulation on the current HIP device.
+ *   dev_mem    device buffer of dev_bytes >= lb_required_bytes(p), owned by
+ *              the caller and outliving the handle; or NULL, in which case the
+ *              library allocates (hipMalloc) and frees the memory itself.
+ *   hip_stream hipStream_t to enqueue all work on (borrowed, may be NULL for
+ *              the null stream).
+ * The populations are zero (rest state) until lb_init. */
+int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_stream,
+              lb_handle** out);
+
+/* Set the populations to the equilibrium of the given fields (the paper does
+ * not state an initial condition; Pi^neq = 0 at start).
+ *   rho[N], u[D*N] host FP64; phi[N] phase field in [-1, 1] for two species
+ *   (rho_R = rho (1+phi)/2, rho_B = rho (1-phi)/2), NULL for one species.
+ * Synchronous with respect to the host arrays.  Resets the step counter.
+ * LB_ENONFINITE if any input is not finite. */
+int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi);
+
+/* Enqueue nsteps >= 0 time steps (moments, then fused stream + collide with
+ * boundaries) on the handle's stream and return without waiting. */
+int lb_step(lb_handle* h, int64_t nsteps);
+
+/* Wait for all work enqueued on the handle's stream. */
+int lb_synchronize(lb_handle* h);
+
+/* Read the moments of the current populations (blocks until done).
+ *   rho[N]      density (rho0 + deviation), or NULL
+ *   u[D*N]      velocity u = (j + F/2)/rho0, or NULL
+ *   pineq[K*N]  non-equilibrium stress, K = D(D+1)/2, or NULL
+ *   phi[N]      phase field (two species only), or NULL
+ *   conserved[6] FP64 device reductions over all nodes: total mass, total
+ *               momentum j (3 components, z = 0 in 2D), red mass, blue mass
+ *               (species 1: red mass = total, blue mass = 0), or NULL.
+ * Moments are evaluated in the handle's compute precision and returned as
+ * FP64.  Returns LB_ENONFINITE (after filling the outputs) if the reduced
+ * mass or momentum is not finite. */
+int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
+               double* conserved);
+
+/* Number of completed time steps since lb_init. */
+int64_t lb_step_count(const lb_handle* h);
+
+/* Destroy a handle (frees library-owned memory).  NULL is accepted. */
+int lb_destroy(lb_handle* h);
+
+/* Static description of a status code.  Never NULL. */
+const char* lb_strerror(int status);
+
+/* ---- instrumentation ------------------------------------------------- */
+
+/* Start per-kernel timing: the next lb_step calls record HIP events around
+ * every moments and stream-collide launch on the handle's stream, for up to
+ * max_steps steps (later steps are not timed). */
+int lb_timing_begin(lb_handle* h, int64_t max_steps);
+
+/* Stop timing (synchronises the stream) and report the summed device time
+ * and launch count of the moments kernel (index 0) and the stream-collide
+ * kernel (index 1).  ms[2], launches[2]. */
+int lb_timing_end(lb_handle* h, double* ms, int64_t* launches);
+
+/* Plain device-to-device copy kernel (bytes a multiple of 16, both pointers
+ * 16-byte aligned), enqueued on hip_stream: the practical bandwidth ceiling
+ * for the sweeps and the scale for hardware byte counters. */
+int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

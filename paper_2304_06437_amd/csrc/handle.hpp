@@ -1,0 +1,139 @@
+// Internal: simulation handle and per-configuration kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lb.h"
+
+namespace lbk {
+
+constexpr int kRedBlocks = 1024;  // blocks of the conservation reduction
+
+struct Layout {
+  int Q = 0, D = 0, M = 0, species = 1;
+  size_t ssize = 0, csize = 0;  // bytes per stored population / per moment
+  int64_t N = 0, npad = 0;
+  size_t f_off = 0, m_off = 0, r_off = 0, total = 0;
+};
+
+struct Impl;
+
+}  // namespace lbk
+
+struct lb_handle {
+  lb_params p;
+  lbk::Layout L;
+  const lbk::Impl* impl = nullptr;
+  void* base = nullptr;
+  bool owned = false;
+  void* f = nullptr;
+  void* m = nullptr;
+  double* partial = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t steps = 0;
+  int v2 = 1;  // nodes per lane of the stream-collide sweep
+  lbk::StepParams<float> p32;
+  lbk::StepParams<double> p64;
+  // per-kernel timing
+  std::vector<hipEvent_t> ev;
+  int64_t tcap = 0, tcount = 0;
+};
+
+namespace lbk {
+
+struct Impl {
+  int v1;
+  int v2max;
+  hipError_t (*moments)(const lb_handle*);
+  hipError_t (*stream_collide)(const lb_handle*);
+  hipError_t (*init)(const lb_handle*, const double*, int64_t, int64_t);
+  hipError_t (*readout)(const lb_handle*, double*, int64_t, int64_t);
+  hipError_t (*conserved)(const lb_handle*);
+};
+
+template <typename C>
+inline const StepParams<C>& params_of(const lb_handle* h);
+template <>
+inline const StepParams<float>& params_of<float>(const lb_handle* h) { return h->p32; }
+template <>
+inline const StepParams<double>& params_of<double>(const lb_handle* h) { return h->p64; }
+
+template <class L, int ORDER, typename S, typename C, int V1, int V2MAX>
+struct ImplT {
+  static hipError_t moments(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    const int64_t threads = p.npad / V1;
+    hipLaunchKernelGGL((k_moments<L, S, C, V1>), dim3((unsigned)((threads + 255) / 256)),
+                       dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
+    return hipGetLastError();
+  }
+  template <int V>
+  static hipError_t sc(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    const int64_t waves = p.nseg * p.ny * p.nz;
+    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, V>), dim3((unsigned)((waves + 3) / 4)),
+                       dim3(256), 0, h->stream, (const C*)h->m, (S*)h->f, p);
+    return hipGetLastError();
+  }
+  static hipError_t stream_collide(const lb_handle* h) {
+    switch (h->v2) {
+      case 8:
+        if constexpr (V2MAX >= 8) return sc<8>(h);
+        break;
+      case 4:
+        if constexpr (V2MAX >= 4) return sc<4>(h);
+        break;
+      case 2:
+        return sc<2>(h);
+      case 1:
+        return sc<1>(h);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t init(const lb_handle* h, const double* stage, int64_t n0, int64_t cnt) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_init<L, ORDER, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                       h->stream, stage, n0, cnt, (S*)h->f, p);
+    return hipGetLastError();
+  }
+  static hipError_t readout(const lb_handle* h, double* out, int64_t n0, int64_t cnt) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_readout<L, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                       h->stream, (const S*)h->f, out, n0, cnt, p);
+    return hipGetLastError();
+  }
+  static hipError_t conserved(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_conserved<L, S, C>), dim3(kRedBlocks), dim3(256), 0, h->stream,
+                       (const S*)h->f, h->partial, h->L.N, p);
+    return hipGetLastError();
+  }
+  static const Impl* get() {
+    static const Impl impl = {V1, V2MAX, &moments, &stream_collide, &init, &readout, &conserved};
+    return &impl;
+  }
+};
+
+template <class L, int ORDER>
+inline const Impl* impl_for_storage(int storage) {
+  constexpr int V2F = (L::Q == 27) ? 4 : 8;
+  constexpr int V2D = (L::Q == 27) ? 2 : 4;
+  switch (storage) {
+    case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, V2D>::get();
+    case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, V2F>::get();
+    case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, V2F>::get();
+    case LB_STORE_BF16S: return ImplT<L, ORDER, bf16s, float, 4, V2F>::get();
+  }
+  return nullptr;
+}
+
+// One translation unit per lattice instantiates its kernels.
+const Impl* impl_d2q9(int storage);
+const Impl* impl_d3q19(int storage);
+const Impl* impl_d3q27(int order, int storage);
+
+}  // namespace lbk

@@ -1,0 +1,6 @@
+// Kernel instantiations for D3Q19.
+#include "handle.hpp"
+
+namespace lbk {
+const Impl* impl_d3q19(int storage) { return impl_for_storage<D3Q19, 2>(storage); }
+}  // namespace lbk

@@ -1,0 +1,538 @@
+// HIP kernels of the thread-safe regularized lattice Boltzmann step (gfx950).
+//
+// One time step (Section 4: moments, then fused streaming + collision, then
+// boundary conditions) is two sweeps over HBM:
+//
+//   moments        f -> m   pointwise: reads the Q population arrays of a node,
+//                           writes its moments drho, j, Pi^neq (M arrays).
+//   stream_collide m -> f   rebuilds every population of every node from the
+//                           moments of the node it streams from (Section 3,
+//                           eq. pushLB with the Hermite-regularized
+//                           non-equilibrium), boundaries fused.  It never reads
+//                           f, so it overwrites the single population set in
+//                           place: no second population array, no even/odd
+//                           step parity, no pointer swap.
+//
+// Work mapping of stream_collide: one 64-lane wavefront owns a segment of
+// 64*V consecutive nodes of one x-row (V per lane).  It loads only that
+// row's moments, turns each node's moments into its post-collision Hermite
+// coefficients once, and then, for every link a,
+//   - takes the source node x - c_a along x from its own registers or from the
+//     neighbouring lane (cross-lane shuffle; the segment ends come from one
+//     extra node on each side),
+//   - stores the V link values into the row (y + c_ay, z + c_az) of array a.
+// Transport along y and z is therefore a store into another row (push form
+// of eq. pushLB), transport along x a register/lane shift (pull form).  Every
+// population f_a(x) is written exactly once per step, by exactly one lane.
+//
+// Halfway bounce-back (Section 5.1): a link a of node x whose neighbour
+// x + c_a lies beyond a wall is written back into the same node as the
+// opposite link, f_abar(x) = f^pc_a(x).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+#include "storage.hpp"
+
+namespace lbk {
+
+template <typename C>
+struct StepParams {
+  int64_t nx, ny, nz;
+  int64_t npad;        // elements between consecutive arrays
+  int64_t nseg;        // row segments per x-row in stream_collide
+  int32_t bbx, bby, bbz;
+  int32_t pad_;
+  C rho0, inv_rho0;
+  C F[3];
+  C halfF[3];
+  C omw;               // 1 - omega
+  C omhw;              // 1 - omega/2
+};
+
+// -------------------------------------------------------------------------
+// Node-level arithmetic.
+// -------------------------------------------------------------------------
+
+// Moments of one node from its shifted populations s_a = f_a - t_a rho0
+// (Section 2 moment definitions; Section 4 moment snippet, where
+// Pi^neq = sum_a f^neq_a c_a c_a, here in its closed form
+// Pi^neq = sum_a s_a c_a c_a - drho cs2 I - rho0 u u, u = (j + F/2)/rho0).
+template <class L, typename C>
+__device__ __forceinline__ void node_moments(const C (&s)[L::Q], const StepParams<C>& p,
+                                             C (&m)[MomentLayout<L>::M]) {
+  using ML = MomentLayout<L>;
+  constexpr int D = L::D;
+  C drho = s[0];
+  C j[D];
+  C P[D][D];
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    j[al] = C(0);
+#pragma unroll
+    for (int be = 0; be < D; ++be) P[al][be] = C(0);
+  }
+#pragma unroll
+  for (int a = 1; a < L::Q; ++a) {
+    drho += s[a];
+#pragma unroll
+    for (int al = 0; al < D; ++al) {
+      if (L::c[a][al] > 0) j[al] += s[a];
+      if (L::c[a][al] < 0) j[al] -= s[a];
+      if (L::c[a][al] != 0) P[al][al] += s[a];
+#pragma unroll
+      for (int be = al + 1; be < D; ++be) {
+        const int cc = L::c[a][al] * L::c[a][be];
+        if (cc > 0) P[al][be] += s[a];
+        if (cc < 0) P[al][be] -= s[a];
+      }
+    }
+  }
+  C u[D];
+#pragma unroll
+  for (int al = 0; al < D; ++al) u[al] = (j[al] + p.halfF[al]) * p.inv_rho0;
+  const C cs2 = C(1.0 / 3.0);
+  m[ML::RHO] = drho;
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    m[ML::J + al] = j[al];
+    m[ML::PID + al] = P[al][al] - drho * cs2 - p.rho0 * u[al] * u[al];
+#pragma unroll
+    for (int be = al + 1; be < D; ++be)
+      m[ML::PIO + offdiag(al, be)] = P[al][be] - p.rho0 * u[al] * u[be];
+  }
+}
+
+// x * NUM / DEN rounded once: the odd part of the reduced denominator is a
+// correctly rounded division, the power-of-two part an exact scaling.
+__host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+
+template <int NUM, int DEN, typename C>
+__device__ __forceinline__ C scaled(C x) {
+  constexpr int g = gcd_int(NUM, DEN);
+  constexpr int n = NUM / g, d = DEN / g;
+  constexpr int d2 = d & -d;  // power-of-two part
+  constexpr int dodd = d / d2;
+  static_assert(n == 1 || dodd == 1, "scaled: single rounding needs n == 1 or odd part 1");
+  C y = x;
+  if constexpr (n != 1) y = y * C(n);
+  if constexpr (dodd != 1) y = y / C(dodd);
+  if constexpr (d2 != 1) y = y * C(1.0 / d2);
+  return y;
+}
+
+// Post-collision Hermite coefficients of a node from its moments.  With
+// J = j + F and u = (j + F/2)/rho0 the post-collision populations are
+//   f^pc_a - t_a rho0 = t_a [ drho + c.J/cs2 + H2_a:A/(2 cs4) (+ H3_a:a3/(6 cs6)) ]
+//   A  = rho0 u u + (1 - omega) Pi^neq + (1 - omega/2)(u F + F u)
+//   a3 = rho0 u u u + (1 - omega)(u Pi^neq + perms)        (order 3, D3Q27)
+// i.e. the equilibrium of eq. equil plus the regularized non-equilibrium of
+// eq. hermite relaxed by (1 - omega) (eq. LBexp), with Guo's source in
+// Hermite form.  The coefficients are prescaled (CoefLayout) so that a link
+// value is a signed sum times a power of two, computed once per node instead
+// of once per link.
+template <class L, int ORDER, typename C>
+__device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
+                                               const StepParams<C>& p,
+                                               C (&k)[CoefLayout<L, ORDER>::K]) {
+  using ML = MomentLayout<L>;
+  using CL = CoefLayout<L, ORDER>;
+  constexpr int D = L::D;
+  constexpr int W = L::wden;
+  C u[D], Jt[D];
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    u[al] = (m[ML::J + al] + p.halfF[al]) * p.inv_rho0;
+    Jt[al] = m[ML::J + al] + p.F[al];
+  }
+  C trA = C(0);
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    const C A = p.rho0 * u[al] * u[al] + p.omw * m[ML::PID + al] + p.omhw * C(2) * u[al] * p.F[al];
+    trA += A;
+    k[CL::AD + al] = scaled<9, 2 * W>(A);   // 4.5 A / wden
+#pragma unroll
+    for (int be = al + 1; be < D; ++be) {
+      const int o = offdiag(al, be);
+      const C Ao = p.rho0 * u[al] * u[be] + p.omw * m[ML::PIO + o] +
+                   p.omhw * (u[al] * p.F[be] + p.F[al] * u[be]);
+      k[CL::AO + o] = scaled<9, W>(Ao);
+    }
+  }
+  k[CL::R] = scaled<1, W>(m[ML::RHO] - C(1.5) * trA);
+#pragma unroll
+  for (int be = 0; be < D; ++be) k[CL::J + be] = scaled<3, W>(Jt[be]);
+  if constexpr (ORDER >= 3) {
+    static_assert(L::Q == 27, "third-order terms need D3Q27");
+    C B[3][3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      B[al][al] = p.omw * m[ML::PID + al];
+#pragma unroll
+      for (int be = al + 1; be < 3; ++be) {
+        B[al][be] = p.omw * m[ML::PIO + offdiag(al, be)];
+        B[be][al] = B[al][be];
+      }
+    }
+    C sum3[3] = {C(0), C(0), C(0)};
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int be = 0; be < 3; ++be) {
+        if (be == al) continue;
+        const C a3 = p.rho0 * u[al] * u[al] * u[be] + C(2) * u[al] * B[al][be] + u[be] * B[al][al];
+        k[CL::T + t3slot(al, be)] = scaled<27, 2 * W>(a3);  // 13.5 a3 / wden
+        sum3[be] += a3;
+      }
+#pragma unroll
+    for (int be = 0; be < 3; ++be) k[CL::J + be] -= scaled<9, 2 * W>(sum3[be]);
+    const C axyz = p.rho0 * u[0] * u[1] * u[2] + u[0] * B[1][2] + u[1] * B[0][2] + u[2] * B[0][1];
+    k[CL::T + 6] = scaled<27, W>(axyz);
+  }
+}
+
+// Shifted post-collision value of link a from prescaled coefficients.
+template <class L, int ORDER, int A, typename C>
+__device__ __forceinline__ C link_value(const C (&k)[CoefLayout<L, ORDER>::K]) {
+  using CL = CoefLayout<L, ORDER>;
+  constexpr int D = L::D;
+  constexpr int c0 = L::c[A][0], c1 = L::c[A][1], c2 = L::c[A][2];
+  constexpr int cv[3] = {c0, c1, c2};
+  C v = k[CL::R];
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    if (cv[al] > 0) v += k[CL::J + al];
+    if (cv[al] < 0) v -= k[CL::J + al];
+  }
+#pragma unroll
+  for (int al = 0; al < D; ++al)
+    if (cv[al] != 0) v += k[CL::AD + al];
+#pragma unroll
+  for (int al = 0; al < D; ++al)
+#pragma unroll
+    for (int be = al + 1; be < D; ++be) {
+      if (cv[al] * cv[be] > 0) v += k[CL::AO + offdiag(al, be)];
+      if (cv[al] * cv[be] < 0) v -= k[CL::AO + offdiag(al, be)];
+    }
+  if constexpr (ORDER >= 3) {
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int be = 0; be < 3; ++be) {
+        if (be == al || cv[al] == 0) continue;
+        if (cv[be] > 0) v += k[CL::T + t3slot(al, be)];
+        if (cv[be] < 0) v -= k[CL::T + t3slot(al, be)];
+      }
+    if (c0 * c1 * c2 > 0) v += k[CL::T + 6];
+    if (c0 * c1 * c2 < 0) v -= k[CL::T + 6];
+  }
+  constexpr int mul = L::wmul[A];
+  if constexpr (mul == 1) return v;
+  else return C(mul) * v;
+}
+
+// -------------------------------------------------------------------------
+// Cross-lane shifts (64-lane wavefront).
+// -------------------------------------------------------------------------
+__device__ __forceinline__ float lane_from_below(float v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ float lane_from_above(float v) { return __shfl_down(v, 1, 64); }
+__device__ __forceinline__ double lane_from_below(double v) { return __shfl_up(v, 1, 64); }
+__device__ __forceinline__ double lane_from_above(double v) { return __shfl_down(v, 1, 64); }
+
+// -------------------------------------------------------------------------
+// Sweep 1: moments.  Each lane handles V consecutive nodes of the flattened
+// (padded) arrays; all loads and stores are V-wide vectors.
+// -------------------------------------------------------------------------
+template <class L, typename S, typename C, int V>
+__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __restrict__ m,
+                                                 StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (i0 >= p.npad) return;
+  C s[L::Q][V];
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
+  C out[ML::M][V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    C se[L::Q], me[ML::M];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) se[a] = s[a][e];
+    node_moments<L, C>(se, p, me);
+#pragma unroll
+    for (int q = 0; q < ML::M; ++q) out[q][e] = me[q];
+  }
+#pragma unroll
+  for (int q = 0; q < ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+}
+
+// -------------------------------------------------------------------------
+// Sweep 2: fused streaming + collision with boundaries.
+// -------------------------------------------------------------------------
+template <class L, int ORDER, typename S, typename C, int V>
+struct StreamCollide {
+  using ML = MomentLayout<L>;
+  using CL = CoefLayout<L, ORDER>;
+  static constexpr int M = ML::M;
+  static constexpr int K = CL::K;
+
+  // Emit link A for this lane's V nodes.
+  template <int A>
+  __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
+                                              const C (&own)[V][K], const C (&left)[K],
+                                              const C (&right)[K], int64_t xs, int64_t y,
+                                              int64_t z, int64_t rowbase) {
+    constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
+    constexpr int AB = opposite<L>(A);
+    // target row of the pushed values
+    int64_t ty = y + cy, tz = z + cz;
+    bool row_in = true;
+    if (cy != 0) {
+      if (ty < 0 || ty >= p.ny) {
+        if (p.bby) row_in = false;
+        else ty = (ty < 0) ? p.ny - 1 : 0;
+      }
+    }
+    if (cz != 0) {
+      if (tz < 0 || tz >= p.nz) {
+        if (p.bbz) row_in = false;
+        else tz = (tz < 0) ? p.nz - 1 : 0;
+      }
+    }
+    if (row_in) {
+      // value arriving at x (this lane's nodes) from source x - cx of this row
+      C val[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if constexpr (cx == 0) {
+          val[e] = link_value<L, ORDER, A, C>(own[e]);
+        } else if constexpr (cx > 0) {
+          val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[e > 0 ? e - 1 : 0])
+                           : link_value<L, ORDER, A, C>(left);
+        } else {
+          val[e] = (e < V - 1) ? link_value<L, ORDER, A, C>(own[e < V - 1 ? e + 1 : 0])
+                               : link_value<L, ORDER, A, C>(right);
+        }
+      }
+      S* dst = f + (int64_t)A * p.npad + p.nx * (ty + p.ny * tz) + xs;
+      const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
+      const bool cut_hi = (cx < 0) && p.bbx && (xs + V == p.nx);    // source x = nx
+      if (!(cut_lo || cut_hi)) {
+        store_pack<S, C, V>(dst, val);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          if ((cut_lo && e == 0) || (cut_hi && e == V - 1)) continue;
+          dst[e] = Codec<S, C>::store(val[e]);
+        }
+      }
+    } else {
+      // every node of this row sends link A across a y/z wall: it comes back
+      // into the same node as the opposite link
+      C bv[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) bv[e] = link_value<L, ORDER, A, C>(own[e]);
+      store_pack<S, C, V>(f + (int64_t)AB * p.npad + rowbase + xs, bv);
+    }
+    if constexpr (cx != 0) {
+      if (row_in && p.bbx) {
+        if (cx > 0 && xs + V == p.nx)
+          f[(int64_t)AB * p.npad + rowbase + p.nx - 1] =
+              Codec<S, C>::store(link_value<L, ORDER, A, C>(own[V - 1]));
+        if (cx < 0 && xs == 0)
+          f[(int64_t)AB * p.npad + rowbase] =
+              Codec<S, C>::store(link_value<L, ORDER, A, C>(own[0]));
+      }
+    }
+  }
+
+  template <int A>
+  __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
+                                               const C (&own)[V][K], const C (&left)[K],
+                                               const C (&right)[K], int64_t xs, int64_t y,
+                                               int64_t z, int64_t rowbase) {
+    if constexpr (A < L::Q) {
+      link<A>(f, p, own, left, right, xs, y, z, rowbase);
+      links<A + 1>(f, p, own, left, right, xs, y, z, rowbase);
+    }
+  }
+
+  __device__ static void load_coef(const C* __restrict__ m, const StepParams<C>& p, int64_t idx,
+                                   C (&k)[K]) {
+    C mm[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) mm[q] = m[(int64_t)q * p.npad + idx];
+    post_collision<L, ORDER, C>(mm, p, k);
+  }
+
+  __device__ static void run(const C* __restrict__ m, S* __restrict__ f, const StepParams<C>& p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t rows = p.ny * p.nz;
+    if (wave >= p.nseg * rows) return;  // whole wavefront leaves together
+    const int64_t seg = wave % p.nseg;
+    const int64_t row = wave / p.nseg;
+    const int64_t y = row % p.ny;
+    const int64_t z = row / p.ny;
+    const int64_t x0 = seg * (64 * V);
+    const int64_t xs = x0 + (int64_t)lane * V;
+    const int64_t xend = (x0 + 64 * V < p.nx) ? x0 + 64 * V : p.nx;
+    const bool active = xs < p.nx;
+    const int64_t rowbase = p.nx * row;
+
+    C own[V][K];
+    if (active) {
+      C mv[M][V];
+#pragma unroll
+      for (int q = 0; q < M; ++q) load_plain<C, V>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        C mm[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) mm[q] = mv[q][e];
+        post_collision<L, ORDER, C>(mm, p, own[e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+#pragma unroll
+        for (int q = 0; q < K; ++q) own[e][q] = C(0);
+    }
+    // x-neighbours of the lane's first and last node
+    C left[K], right[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      left[q] = lane_from_below(own[V - 1][q]);
+      right[q] = lane_from_above(own[0][q]);
+    }
+    if (lane == 0) {
+      int64_t xl = x0 - 1;
+      bool ok = true;
+      if (xl < 0) {
+        if (p.bbx) ok = false;
+        else xl = p.nx - 1;
+      }
+      if (ok) load_coef(m, p, rowbase + xl, left);
+    }
+    if (active && xs + V == xend) {
+      int64_t xr = xend;
+      bool ok = true;
+      if (xr >= p.nx) {
+        if (p.bbx) ok = false;
+        else xr = 0;
+      }
+      if (ok) load_coef(m, p, rowbase + xr, right);
+    }
+    if (!active) return;
+    links<0>(f, p, own, left, right, xs, y, z, rowbase);
+  }
+};
+
+template <class L, int ORDER, typename S, typename C, int V>
+__global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
+                                                        S* __restrict__ f, StepParams<C> p) {
+  StreamCollide<L, ORDER, S, C, V>::run(m, f, p);
+}
+
+// -------------------------------------------------------------------------
+// Initialisation: populations at equilibrium of given fields (Pi^neq = 0).
+// stage holds (1 + D) x cnt doubles: drho, then u.
+// -------------------------------------------------------------------------
+template <class L, int ORDER, typename S, typename C, int A>
+__device__ __forceinline__ void init_links(S* __restrict__ f, int64_t npad, int64_t n,
+                                           const C (&k)[CoefLayout<L, ORDER>::K]) {
+  if constexpr (A < L::Q) {
+    f[(int64_t)A * npad + n] = Codec<S, C>::store(link_value<L, ORDER, A, C>(k));
+    init_links<L, ORDER, S, C, A + 1>(f, npad, n, k);
+  }
+}
+
+template <class L, int ORDER, typename S, typename C>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ stage, int64_t n0,
+                                              int64_t cnt, S* __restrict__ f, StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  using CL = CoefLayout<L, ORDER>;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  C mm[ML::M];
+#pragma unroll
+  for (int q = 0; q < ML::M; ++q) mm[q] = C(0);
+  mm[ML::RHO] = (C)stage[i];
+#pragma unroll
+  for (int al = 0; al < L::D; ++al) mm[ML::J + al] = p.rho0 * (C)stage[(int64_t)(1 + al) * cnt + i];
+  StepParams<C> q = p;  // equilibrium: no force, no non-equilibrium part
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    q.F[al] = C(0);
+    q.halfF[al] = C(0);
+  }
+  C k[CL::K];
+  post_collision<L, ORDER, C>(mm, q, k);
+  init_links<L, ORDER, S, C, 0>(f, p.npad, n0 + i, k);
+}
+
+// -------------------------------------------------------------------------
+// Moment read-out for the host: rho, u, Pi^neq of nodes [n0, n0 + cnt) as
+// FP64, (1 + D + D(D+1)/2) x cnt.
+// -------------------------------------------------------------------------
+template <class L, typename S, typename C>
+__global__ __launch_bounds__(256) void k_readout(const S* __restrict__ f, double* __restrict__ out,
+                                                 int64_t n0, int64_t cnt, StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  constexpr int D = L::D;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t n = n0 + i;
+  C s[L::Q], me[ML::M];
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) s[a] = Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+  node_moments<L, C>(s, p, me);
+  out[i] = (double)p.rho0 + (double)me[ML::RHO];  // keep the deviation's digits
+#pragma unroll
+  for (int al = 0; al < D; ++al)
+    out[(int64_t)(1 + al) * cnt + i] = (double)((me[ML::J + al] + p.halfF[al]) * p.inv_rho0);
+#pragma unroll
+  for (int q = 0; q < D * (D + 1) / 2; ++q)
+    out[(int64_t)(1 + D + q) * cnt + i] = (double)me[ML::PID + q];
+}
+
+// -------------------------------------------------------------------------
+// FP64 conservation reductions: sum over nodes of drho and j.
+// partial[block * 8 + {0: drho, 1..3: j}].
+// -------------------------------------------------------------------------
+template <class L, typename S, typename C>
+__global__ __launch_bounds__(256) void k_conserved(const S* __restrict__ f,
+                                                   double* __restrict__ partial, int64_t N,
+                                                   StepParams<C> p) {
+  __shared__ double red[4][256];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+      const double s = (double)Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+      acc[0] += s;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        if (L::c[a][al] > 0) acc[1 + al] += s;
+        if (L::c[a][al] < 0) acc[1 + al] -= s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) partial[(int64_t)blockIdx.x * 8 + q] = red[q][0];
+}
+
+}  // namespace lbk

@@ -1,0 +1,436 @@
+// Host side of liblb.so: the C ABI declared in include/lb.h.
+//
+// Device memory of one simulation (lb_required_bytes):
+//   f  species*Q population arrays, storage type, shifted (f_a - t_a rho0)
+//   m  M moment arrays (drho, j, Pi^neq), compute type
+//   r  FP64 partial sums of the conservation reduction
+// Every array holds npad >= N elements (npad a multiple of 4096), so every
+// array starts 256-byte aligned and the moments sweep needs no tail.
+// lb_init and lb_moments stage their host transfers through m, which the
+// next step's moments sweep rewrites anyway; the library allocates nothing
+// beyond lb_required_bytes on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "handle.hpp"
+#include "lb.h"
+
+namespace {
+
+using namespace lbk;
+
+// -------------------------------------------------------------------------
+// Plain copy (bandwidth ceiling and byte-counter scale).
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
+                                              uint4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
+
+constexpr int64_t kPadNodes = 4096;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int status_of(hipError_t e) {
+  if (e == hipSuccess) return LB_OK;
+  if (e == hipErrorOutOfMemory) return LB_ENOMEM;
+  return LB_EDEVICE;
+}
+
+#define LB_TRY_HIP(expr)                  \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return status_of(e_); \
+  } while (0)
+
+int lattice_q(int lattice) {
+  return lattice == LB_D2Q9 ? 9 : lattice == LB_D3Q19 ? 19 : lattice == LB_D3Q27 ? 27 : 0;
+}
+
+int validate(const lb_params* p) {
+  if (!p) return LB_EINVAL;
+  if (p->struct_size != sizeof(lb_params)) return LB_EINVAL;
+  const int Q = lattice_q(p->lattice);
+  if (!Q) return LB_EINVAL;
+  if (p->hermite_order != 2 && p->hermite_order != 3) return LB_EINVAL;
+  if (p->hermite_order == 3 && p->lattice != LB_D3Q27) return LB_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LB_EINVAL;
+  if (p->lattice == LB_D2Q9 && p->nz != 1) return LB_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != LB_PERIODIC && p->bc[a] != LB_BOUNCEBACK) return LB_EINVAL;
+  if (p->lattice == LB_D2Q9 && p->bc[2] != LB_PERIODIC) return LB_EINVAL;
+  if (!(std::isfinite(p->tau) && p->tau > 0.5)) return LB_EINVAL;
+  if (!(std::isfinite(p->rho0) && p->rho0 > 0.0)) return LB_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) return LB_EINVAL;
+  if (p->lattice == LB_D2Q9 && p->force[2] != 0.0) return LB_EINVAL;
+  if (p->species != 1 && p->species != 2) return LB_EINVAL;
+  if (p->species == 2) {
+    if (!(std::isfinite(p->sigma) && p->sigma >= 0.0)) return LB_EINVAL;
+    if (!(std::isfinite(p->beta) && p->beta >= 0.0 && p->beta <= 1.0)) return LB_EINVAL;
+    if (p->lattice == LB_D3Q27) return LB_EINVAL;  // no published B_a set used here
+    return LB_EUNSUPPORTED;
+  }
+  const bool f64 = p->compute == LB_COMPUTE_F64;
+  const bool f32 = p->compute == LB_COMPUTE_F32;
+  if (!f64 && !f32) return LB_EINVAL;
+  switch (p->storage) {
+    case LB_STORE_F64:
+      if (!f64) return LB_EINVAL;
+      break;
+    case LB_STORE_F32:
+    case LB_STORE_F16S:
+    case LB_STORE_BF16S:
+      if (!f32) return LB_EINVAL;
+      break;
+    default:
+      return LB_EINVAL;
+  }
+  // keep every index comfortably inside int64
+  const double N = (double)p->nx * (double)p->ny * (double)p->nz;
+  if (N > 4.0e12) return LB_EINVAL;
+  return LB_OK;
+}
+
+Layout layout_of(const lb_params* p) {
+  Layout L;
+  L.Q = lattice_q(p->lattice);
+  L.D = p->lattice == LB_D2Q9 ? 2 : 3;
+  L.M = 1 + L.D + L.D * (L.D + 1) / 2;
+  L.species = p->species;
+  L.ssize = p->storage == LB_STORE_F64 ? 8 : p->storage == LB_STORE_F32 ? 4 : 2;
+  L.csize = p->compute == LB_COMPUTE_F64 ? 8 : 4;
+  L.N = p->nx * p->ny * p->nz;
+  L.npad = (L.N + kPadNodes - 1) / kPadNodes * kPadNodes;
+  L.f_off = 0;
+  L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
+  L.r_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
+  L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
+  return L;
+}
+
+const Impl* select_impl(const lb_params* p) {
+  switch (p->lattice) {
+    case LB_D2Q9: return impl_d2q9(p->storage);
+    case LB_D3Q19: return impl_d3q19(p->storage);
+    case LB_D3Q27: return impl_d3q27(p->hermite_order, p->storage);
+  }
+  return nullptr;
+}
+
+// Nodes per lane of the stream-collide sweep: the widest V <= vmax that
+// divides nx (aligned V-wide vector access) and still fills a wavefront
+// (64 V <= nx); V = 1 otherwise.
+int choose_v2(int64_t nx, int vmax) {
+  for (int v = vmax; v >= 1; v >>= 1)
+    if (nx % v == 0 && 64 * v <= nx) return v;
+  return 1;
+}
+
+template <typename C>
+void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) {
+  q.nx = p->nx;
+  q.ny = p->ny;
+  q.nz = p->nz;
+  q.npad = L.npad;
+  q.nseg = (p->nx + 64 * v2 - 1) / (64 * v2);
+  q.bbx = p->bc[0] == LB_BOUNCEBACK;
+  q.bby = p->bc[1] == LB_BOUNCEBACK;
+  q.bbz = p->bc[2] == LB_BOUNCEBACK;
+  q.pad_ = 0;
+  q.rho0 = (C)p->rho0;
+  q.inv_rho0 = (C)(1.0 / p->rho0);
+  for (int a = 0; a < 3; ++a) {
+    q.F[a] = (C)p->force[a];
+    q.halfF[a] = (C)(0.5 * p->force[a]);
+  }
+  const double omega = 1.0 / p->tau;
+  q.omw = (C)(1.0 - omega);
+  q.omhw = (C)(1.0 - 0.5 * omega);
+}
+
+int launch_status(hipError_t e) { return status_of(e); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void lb_params_default(lb_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(lb_params);
+  p->lattice = LB_D3Q19;
+  p->hermite_order = 2;
+  p->nx = p->ny = p->nz = 32;
+  p->bc[0] = p->bc[1] = p->bc[2] = LB_PERIODIC;
+  p->species = 1;
+  p->tau = 0.6;
+  p->rho0 = 1.0;
+  p->sigma = 0.0;
+  p->beta = 0.0;
+  p->storage = LB_STORE_F32;
+  p->compute = LB_COMPUTE_F32;
+}
+
+int lb_validate(const lb_params* p) { return validate(p); }
+
+size_t lb_required_bytes(const lb_params* p) {
+  if (validate(p) != LB_OK) return 0;
+  return layout_of(p).total;
+}
+
+int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_stream,
+              lb_handle** out) {
+  if (!out) return LB_EINVAL;
+  *out = nullptr;
+  const int st = validate(p);
+  if (st != LB_OK) return st;
+  try {
+    lb_handle* h = new lb_handle();
+    h->p = *p;
+    h->L = layout_of(p);
+    h->impl = select_impl(p);
+    if (!h->impl) {
+      delete h;
+      return LB_EUNSUPPORTED;
+    }
+    h->stream = (hipStream_t)hip_stream;
+    h->v2 = choose_v2(p->nx, h->impl->v2max);
+    if (dev_mem) {
+      if (dev_bytes < h->L.total || ((uintptr_t)dev_mem % kAlign) != 0) {
+        delete h;
+        return LB_ENOMEM;
+      }
+      h->base = dev_mem;
+      h->owned = false;
+    } else {
+      hipError_t e = hipMalloc(&h->base, h->L.total);
+      if (e != hipSuccess) {
+        delete h;
+        return status_of(e);
+      }
+      h->owned = true;
+    }
+    h->f = (char*)h->base + h->L.f_off;
+    h->m = (char*)h->base + h->L.m_off;
+    h->partial = (double*)((char*)h->base + h->L.r_off);
+    fill_params(h->p32, p, h->L, h->v2);
+    fill_params(h->p64, p, h->L, h->v2);
+    hipError_t e = hipMemsetAsync(h->base, 0, h->L.total, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      if (h->owned) (void)hipFree(h->base);
+      delete h;
+      return status_of(e);
+    }
+    *out = h;
+    return LB_OK;
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  } catch (...) {
+    return LB_EDEVICE;
+  }
+}
+
+int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi) {
+  if (!h || !rho || !u) return LB_EINVAL;
+  if (h->p.species == 2 && !phi) return LB_EINVAL;
+  const Layout& L = h->L;
+  const int64_t N = L.N;
+  for (int64_t n = 0; n < N; ++n)
+    if (!std::isfinite(rho[n])) return LB_ENONFINITE;
+  for (int64_t n = 0; n < (int64_t)L.D * N; ++n)
+    if (!std::isfinite(u[n])) return LB_ENONFINITE;
+  try {
+    const int per = 1 + L.D;  // doubles staged per node
+    const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
+    const int64_t chunk = cap < N ? cap : N;
+    std::vector<double> hb((size_t)per * chunk);
+    double* stage = (double*)h->m;
+    for (int64_t n0 = 0; n0 < N; n0 += chunk) {
+      const int64_t cnt = (N - n0 < chunk) ? N - n0 : chunk;
+      for (int64_t i = 0; i < cnt; ++i) hb[i] = rho[n0 + i] - h->p.rho0;
+      for (int al = 0; al < L.D; ++al)
+        std::memcpy(&hb[(size_t)(1 + al) * cnt], u + (size_t)al * N + n0, cnt * sizeof(double));
+      LB_TRY_HIP(hipMemcpyAsync(stage, hb.data(), (size_t)per * cnt * sizeof(double),
+                                hipMemcpyHostToDevice, h->stream));
+      LB_TRY_HIP(h->impl->init(h, stage, n0, cnt));
+      LB_TRY_HIP(hipStreamSynchronize(h->stream));
+    }
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  }
+  h->steps = 0;
+  return LB_OK;
+}
+
+int lb_step(lb_handle* h, int64_t nsteps) {
+  if (!h || nsteps < 0) return LB_EINVAL;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const bool timed = h->tcount < h->tcap;
+    hipEvent_t* ev = timed ? &h->ev[(size_t)4 * h->tcount] : nullptr;
+    if (timed) LB_TRY_HIP(hipEventRecord(ev[0], h->stream));
+    LB_TRY_HIP(h->impl->moments(h));
+    if (timed) LB_TRY_HIP(hipEventRecord(ev[1], h->stream));
+    if (timed) LB_TRY_HIP(hipEventRecord(ev[2], h->stream));
+    LB_TRY_HIP(h->impl->stream_collide(h));
+    if (timed) {
+      LB_TRY_HIP(hipEventRecord(ev[3], h->stream));
+      ++h->tcount;
+    }
+    ++h->steps;
+  }
+  return LB_OK;
+}
+
+int lb_synchronize(lb_handle* h) {
+  if (!h) return LB_EINVAL;
+  return launch_status(hipStreamSynchronize(h->stream));
+}
+
+int64_t lb_step_count(const lb_handle* h) { return h ? h->steps : -1; }
+
+int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
+               double* conserved) {
+  if (!h) return LB_EINVAL;
+  (void)phi;
+  const Layout& L = h->L;
+  const int64_t N = L.N;
+  const int K = L.D * (L.D + 1) / 2;
+  const int per = 1 + L.D + K;
+  try {
+    if (rho || u || pineq) {
+      const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
+      const int64_t chunk = cap < N ? cap : N;
+      std::vector<double> hb((size_t)per * chunk);
+      double* stage = (double*)h->m;
+      for (int64_t n0 = 0; n0 < N; n0 += chunk) {
+        const int64_t cnt = (N - n0 < chunk) ? N - n0 : chunk;
+        LB_TRY_HIP(h->impl->readout(h, stage, n0, cnt));
+        LB_TRY_HIP(hipMemcpyAsync(hb.data(), stage, (size_t)per * cnt * sizeof(double),
+                                  hipMemcpyDeviceToHost, h->stream));
+        LB_TRY_HIP(hipStreamSynchronize(h->stream));
+        if (rho) std::memcpy(rho + n0, hb.data(), cnt * sizeof(double));
+        if (u)
+          for (int al = 0; al < L.D; ++al)
+            std::memcpy(u + (size_t)al * N + n0, &hb[(size_t)(1 + al) * cnt], cnt * sizeof(double));
+        if (pineq)
+          for (int q = 0; q < K; ++q)
+            std::memcpy(pineq + (size_t)q * N + n0, &hb[(size_t)(1 + L.D + q) * cnt],
+                        cnt * sizeof(double));
+      }
+    }
+    int st = LB_OK;
+    if (conserved) {
+      std::vector<double> part((size_t)kRedBlocks * 8);
+      LB_TRY_HIP(h->impl->conserved(h));
+      LB_TRY_HIP(hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream));
+      LB_TRY_HIP(hipStreamSynchronize(h->stream));
+      double acc[4] = {0, 0, 0, 0};
+      for (int b = 0; b < kRedBlocks; ++b)
+        for (int q = 0; q < 4; ++q) acc[q] += part[(size_t)b * 8 + q];
+      conserved[0] = (double)N * h->p.rho0 + acc[0];
+      conserved[1] = acc[1];
+      conserved[2] = acc[2];
+      conserved[3] = acc[3];
+      conserved[4] = conserved[0];
+      conserved[5] = 0.0;
+      for (int q = 0; q < 4; ++q)
+        if (!std::isfinite(conserved[q])) st = LB_ENONFINITE;
+    } else {
+      LB_TRY_HIP(hipStreamSynchronize(h->stream));
+    }
+    return st;
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  }
+}
+
+int lb_destroy(lb_handle* h) {
+  if (!h) return LB_OK;
+  int st = LB_OK;
+  hipError_t se = hipStreamSynchronize(h->stream);
+  if (se != hipSuccess) st = status_of(se);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->owned && h->base) {
+    hipError_t e = hipFree(h->base);
+    if (e != hipSuccess && st == LB_OK) st = status_of(e);
+  }
+  delete h;
+  return st;
+}
+
+const char* lb_strerror(int status) {
+  switch (status) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument or parameter combination";
+    case LB_ENOMEM: return "out of memory or buffer too small";
+    case LB_EUNSUPPORTED: return "not supported by this build";
+    case LB_EDEVICE: return "HIP runtime error";
+    case LB_ENONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+int lb_timing_begin(lb_handle* h, int64_t max_steps) {
+  if (!h || max_steps < 0) return LB_EINVAL;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+  h->tcap = 0;
+  h->tcount = 0;
+  try {
+    h->ev.resize((size_t)4 * max_steps, nullptr);
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  }
+  for (auto& e : h->ev) LB_TRY_HIP(hipEventCreate(&e));
+  h->tcap = max_steps;
+  return LB_OK;
+}
+
+int lb_timing_end(lb_handle* h, double* ms, int64_t* launches) {
+  if (!h || !ms || !launches) return LB_EINVAL;
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  double t[2] = {0.0, 0.0};
+  for (int64_t s = 0; s < h->tcount; ++s) {
+    float a = 0.f, b = 0.f;
+    LB_TRY_HIP(hipEventElapsedTime(&a, h->ev[(size_t)4 * s], h->ev[(size_t)4 * s + 1]));
+    LB_TRY_HIP(hipEventElapsedTime(&b, h->ev[(size_t)4 * s + 2], h->ev[(size_t)4 * s + 3]));
+    t[0] += a;
+    t[1] += b;
+  }
+  ms[0] = t[0];
+  ms[1] = t[1];
+  launches[0] = launches[1] = h->tcount;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+  h->tcap = h->tcount = 0;
+  return LB_OK;
+}
+
+int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+    return LB_EINVAL;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return LB_OK;
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     (const uint4*)src, (uint4*)dst, n16);
+  return launch_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI (no GPU needed: nothing here launches work)."""
+import os
+import subprocess
+
+import pytest
+
+from paper_2304_06437_amd import lb
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_library_exports_every_declared_function():
+    lib = lb.load()
+    declared = lb.header_functions()
+    assert "lb_create" in declared and "lb_step" in declared and "lb_moments" in declared
+    nm = subprocess.run(["nm", "-D", "--defined-only", lb.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    exported = {line.split()[-1] for line in nm.splitlines() if line.strip()}
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name), name
+
+
+def test_params_default_is_valid():
+    p = lb.lb_params_default()
+    assert lb.lb_validate(p) == lb.LB_OK
+    assert (p.lattice, p.nx, p.ny, p.nz, p.species) == (lb.LB_D3Q19, 32, 32, 32, 1)
+    assert p.storage == lb.LB_STORE_F32 and p.compute == lb.LB_COMPUTE_F32
+
+
+def test_struct_size_matches_c_layout():
+    import ctypes
+    p = lb.lb_params_default()
+    assert p.struct_size == ctypes.sizeof(lb.lb_params)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tau", 0.5), ("tau", float("nan")), ("rho0", 0.0), ("lattice", 15),
+    ("hermite_order", 4), ("nx", 0), ("storage", 9), ("compute", 5),
+])
+def test_invalid_parameters_rejected(field, value):
+    p = lb.lb_params_default(**{field: value})
+    assert lb.lb_validate(p) == lb.LB_EINVAL
+    assert lb.lb_required_bytes(p) == 0
+    with pytest.raises(lb.LbError) as e:
+        lb.lb_create(p)
+    assert e.value.status == lb.LB_EINVAL
+
+
+def test_invalid_combinations_rejected():
+    assert lb.lb_validate(lb.lb_params_default(hermite_order=3)) == lb.LB_EINVAL  # D3Q19
+    assert lb.lb_validate(lb.lb_params_default(lattice=27, hermite_order=3)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(lattice=9, nz=2)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(lattice=9, nz=1)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(lattice=9, nz=1, bc=(0, 0, 1))) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(storage=lb.LB_STORE_F64)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(storage=lb.LB_STORE_F64,
+                                               compute=lb.LB_COMPUTE_F64)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(storage=lb.LB_STORE_F16S,
+                                               compute=lb.LB_COMPUTE_F64)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(bc=(2, 0, 0))) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(force=(float("inf"), 0, 0))) == lb.LB_EINVAL
+    p = lb.lb_params_default()
+    p.struct_size = 8
+    assert lb.lb_validate(p) == lb.LB_EINVAL
+
+
+def _golden_arrays():
+    rows = {}
+    for line in open(os.path.join(HERE, "golden", "memory_arrays.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, ts, ff, save = line.split()
+        rows[name] = (int(ts), int(ff), int(save))
+    return rows
+
+
+def test_required_bytes_match_paper_array_counts():
+    """Section 4: 15 (D2Q9) and 29 (D3Q19) single-precision arrays per node."""
+    g = _golden_arrays()
+    for name, lattice, nz in (("D2Q9", 9, 1), ("D3Q19", 19, 256)):
+        p = lb.lb_params_default(lattice=lattice, nx=256, ny=256, nz=nz)
+        N = 256 * 256 * nz
+        arrays = g[name][0]
+        extra = lb.lb_required_bytes(p) - arrays * 4 * N
+        # only the FP64 reduction scratch (64 KiB) and alignment remain
+        assert 0 <= extra <= 64 * 1024 + 256 * (arrays + 2), (name, extra)
+        # saving against the flip-flop layout, bytes per node (Section 4)
+        assert (g[name][1] - arrays) * 4 == g[name][2]
+
+
+def test_required_bytes_scale_with_precision():
+    base = dict(nx=128, ny=128, nz=128)
+    b32 = lb.lb_required_bytes(lb.lb_params_default(**base))
+    b16 = lb.lb_required_bytes(lb.lb_params_default(storage=lb.LB_STORE_F16S, **base))
+    b64 = lb.lb_required_bytes(lb.lb_params_default(storage=lb.LB_STORE_F64,
+                                                    compute=lb.LB_COMPUTE_F64, **base))
+    N = 128 ** 3
+    assert abs((b32 - b16) - 19 * 2 * N) < 4096
+    assert abs((b64 - b32) - 29 * 4 * N) < 4096
+
+
+def test_strerror_and_null_destroy():
+    for st in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(lb.lb_strerror(st), str) and lb.lb_strerror(st)
+    assert lb.load().lb_destroy(None) == lb.LB_OK
+    assert lb.load().lb_step(None, 1) == lb.LB_EINVAL
+    assert lb.load().lb_moments(None, None, None, None, None, None) == lb.LB_EINVAL
+    assert lb.load().lb_copy(None, None, 16, None) == lb.LB_EINVAL

@@ -1,0 +1,260 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP32 storage and compute): velocity max-relative error
+max|u_gpu - u_ref| / max|u_ref| <= 1e-5 after up to 1000 steps.  FP64 mode:
+<= 1e-11.  16-bit storage modes: error reported (printed), sanity-bounded
+only.  Sizes span several row segments with ragged tails; the last test runs
+the benchmark's 512^3 configuration and checks sampled nodes against the
+oracle evaluated on each sample's dependency cone.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_06437_amd import inputs, lb
+from paper_2304_06437_amd.sim import Simulation, make_params, max_rel, run
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-11
+
+
+def _fields(flow, lattice, shape, seed=0):
+    nx, ny, nz = shape
+    D = 2 if lattice == 9 else 3
+    N = nx * ny * nz
+    if flow == "tg2d":
+        return inputs.taylor_green_2d(nx, ny, 0.01)
+    if flow == "tg3d":
+        return inputs.taylor_green_3d(nx, ny, nz, 0.02)
+    if flow == "channel":
+        return inputs.channel_noise(nx, ny, nz, D)
+    if flow == "random":
+        return inputs.random_state(N, D, seed=seed, drho=1e-3, du=0.02)
+    if flow == "shear":
+        return inputs.shear_wave(nx, ny, nz, D, 0.01, axis_u=1, axis_k=0)
+    raise ValueError(flow)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle(lattice, shape, tau, steps, flow, force, bc, order, seed=0):
+    rho, u = _fields(flow, lattice, shape, seed)
+    p = oracle.Params(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2], tau=tau,
+                      force=force, bb=bc, order=order)
+    return oracle.simulate(p, rho, u, steps)
+
+
+def _gpu(lattice, shape, tau, steps, flow, force, bc, order, storage, seed=0):
+    rho, u = _fields(flow, lattice, shape, seed)
+    p = make_params(lattice=lattice, shape=shape, tau=tau, force=force, bc=bc, order=order,
+                    storage=storage)
+    return run(p, rho, u, steps)
+
+
+CASES = {
+    # name: (lattice, shape, tau, steps, flow, force, bc, order)
+    "tg3d_d3q19_ragged_1000": (19, (96, 24, 20), 0.55, 1000, "tg3d", (0, 0, 0), (0, 0, 0), 2),
+    "tg3d_d3q19_two_segments_v2": (19, (200, 8, 6), 0.6, 400, "tg3d", (0, 0, 0), (0, 0, 0), 2),
+    "tg3d_d3q19_two_segments_v8": (19, (1024, 4, 3), 0.6, 300, "tg3d", (0, 0, 0), (0, 0, 0), 2),
+    "channel_d3q19_1000": (19, (64, 12, 24), 0.6, 1000, "channel", (1e-5, 0, 0), (0, 0, 1), 2),
+    "tg2d_d2q9_1000": (9, (128, 128, 1), 0.8, 1000, "tg2d", (0, 0, 0), (0, 0, 0), 2),
+    "walls_xy_d2q9_ragged": (9, (67, 45, 1), 0.7, 500, "random", (1e-5, -2e-5, 0), (1, 1, 0), 2),
+    "box_walls_d3q19": (19, (20, 9, 7), 0.6, 300, "random", (1e-5, 2e-5, -1e-5), (1, 1, 1), 2),
+    "tg3d_d3q27_order3": (27, (40, 16, 12), 0.55, 500, "tg3d", (0, 0, 0), (0, 0, 0), 3),
+    "walls_y_d3q27_order2": (27, (24, 10, 8), 0.6, 300, "random", (1e-5, 0, 2e-5), (0, 1, 0), 2),
+    "walls_xz_d3q27_order3": (27, (17, 6, 9), 0.65, 200, "random", (0, 1e-5, 0), (1, 0, 1), 3),
+    "line_x_d3q19": (19, (64, 1, 1), 0.6, 300, "shear", (0, 0, 0), (0, 0, 0), 2),
+    "column_z_walls_d3q19": (19, (1, 1, 32), 0.8, 1000, "channel", (1e-5, 0, 0), (0, 0, 1), 2),
+    "single_node_d3q19": (19, (1, 1, 1), 0.7, 20, "random", (1e-4, 0, 0), (0, 0, 0), 2),
+    "plane_y1_d3q27": (27, (33, 1, 5), 0.7, 100, "random", (0, 0, 0), (0, 0, 1), 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp32_matches_oracle(name):
+    case = CASES[name]
+    ref = _oracle(*case)
+    got = _gpu(*case, storage="f32")
+    err_u = max_rel(got["u"], ref["u"])
+    err_rho = float(np.abs(got["rho"] - ref["rho"]).max())
+    err_pi = max_rel(got["pineq"], ref["pineq"])
+    print(f"{name}: max-rel u {err_u:.3e}, |drho| {err_rho:.3e}, max-rel Pi {err_pi:.3e}")
+    assert err_u <= FP32_TOL, err_u
+    assert err_rho <= 1e-6
+    assert err_pi <= 1e-3
+
+
+FP64_CASES = ["tg2d_d2q9_1000", "channel_d3q19_1000", "tg3d_d3q27_order3", "box_walls_d3q19",
+              "walls_xz_d3q27_order3"]
+
+
+@pytest.mark.parametrize("name", FP64_CASES)
+def test_fp64_matches_oracle(name):
+    case = CASES[name]
+    ref = _oracle(*case)
+    got = _gpu(*case, storage="f64")
+    err_u = max_rel(got["u"], ref["u"])
+    err_pi = max_rel(got["pineq"], ref["pineq"])
+    print(f"{name} fp64: max-rel u {err_u:.3e}, max-rel Pi {err_pi:.3e}")
+    assert err_u <= FP64_TOL
+    assert np.abs(got["rho"] - ref["rho"]).max() <= 1e-13
+    assert err_pi <= 1e-9
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_reduced_precision_storage_error_reported(storage):
+    """16-bit shifted population storage: error against the FP64 oracle is
+    reported, not held to the FP32 bar (parity unpinned)."""
+    for name in ("tg3d_d3q19_ragged_1000", "tg3d_d3q27_order3", "channel_d3q19_1000"):
+        case = CASES[name]
+        ref = _oracle(*case)
+        got = _gpu(*case, storage=storage)
+        err = max_rel(got["u"], ref["u"])
+        print(f"{name} {storage}: max-rel u {err:.3e}")
+        assert np.isfinite(got["u"]).all()
+        assert err < 0.5
+
+
+def test_channel_2000_steps_error_reported():
+    """The 256^3 channel workload's physics on a 4 x 4 x 256 column (uniform
+    in x and y; walls in z, g = 1e-6, tau = 0.6, seeded density noise,
+    2000 steps).  In forced flow the per-step momentum increment is a few
+    thousand ulps of the stored FP32 populations, so storage quantization can
+    act coherently over many steps; the error is reported and held to 1e-4."""
+    case = (19, (4, 4, 256), 0.6, 2000, "channel", (1e-6, 0, 0), (0, 0, 1), 2)
+    ref = _oracle(*case)
+    for storage in ("f32", "f64"):
+        got = _gpu(*case, storage=storage)
+        err = max_rel(got["u"], ref["u"])
+        print(f"channel 4x4x256 2000 steps {storage}: max-rel u {err:.3e}")
+        assert err < (1e-4 if storage == "f32" else FP64_TOL)
+
+
+def test_rest_state_is_exactly_kept():
+    """Shifted storage keeps the rest state exactly (all deviations are 0)."""
+    for lattice, shape, bc, order in ((19, (40, 6, 5), (1, 0, 1), 2), (9, (70, 9, 1), (0, 1, 0), 2),
+                                      (27, (9, 8, 7), (1, 1, 1), 3)):
+        p = make_params(lattice=lattice, shape=shape, tau=0.6, bc=bc, order=order)
+        N = shape[0] * shape[1] * shape[2]
+        D = 2 if lattice == 9 else 3
+        got = run(p, np.ones(N), np.zeros((D, N)), 50)
+        assert np.array_equal(got["rho"], np.ones(N))
+        assert not got["u"].any() and not got["pineq"].any()
+
+
+def test_conservation_reductions():
+    """FP64 device reductions: mass is kept, periodic momentum gains N F per step."""
+    shape = (48, 20, 16)
+    N = shape[0] * shape[1] * shape[2]
+    F = np.array([1e-5, -2e-5, 3e-5])
+    rho, u = inputs.random_state(N, 3, seed=5, drho=1e-3, du=0.02)
+    for storage, tol in (("f32", 1e-9), ("f64", 1e-13)):
+        p = make_params(lattice=19, shape=shape, tau=0.6, force=tuple(F), storage=storage)
+        with Simulation(p) as sim:
+            sim.init(rho, u)
+            c0 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
+            sim.step(200)
+            c1 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
+        assert abs(c0[0] - rho.sum()) / N < 1e-9
+        np.testing.assert_allclose(c0[1:4], u.sum(axis=1), rtol=0, atol=N * 1e-9)
+        assert abs(c1[0] - c0[0]) / N < tol, (storage, c1[0] - c0[0])
+        np.testing.assert_allclose(c1[1:4] - c0[1:4], 200 * N * F, rtol=1e-5)
+        assert c1[4] == c1[0] and c1[5] == 0.0
+
+
+def test_walls_conserve_mass():
+    shape = (30, 10, 12)
+    N = shape[0] * shape[1] * shape[2]
+    rho, u = inputs.random_state(N, 3, seed=6, drho=1e-3, du=0.02)
+    p = make_params(lattice=19, shape=shape, tau=0.6, force=(1e-5, 0, 0), bc=(1, 1, 1))
+    with Simulation(p) as sim:
+        sim.init(rho, u)
+        m0 = sim.moments(rho=False, u=False, pineq=False)["conserved"][0]
+        sim.step(300)
+        m1 = sim.moments(rho=False, u=False, pineq=False)["conserved"][0]
+    assert abs(m1 - m0) / N < 1e-9
+
+
+def test_translation_equivariance_yz_bitwise():
+    """Rolling the initial fields along y and z rolls the GPU result bitwise
+    (every row is processed by identical code)."""
+    shape = (128, 12, 10)
+    rho, u = inputs.random_state(shape[0] * shape[1] * shape[2], 3, seed=8, drho=1e-3, du=0.02)
+    p = make_params(lattice=19, shape=shape, tau=0.6, force=(1e-5, 0, 0))
+
+    def roll(a):
+        return np.roll(a.reshape(-1, shape[2], shape[1], shape[0]), (3, 5), axis=(1, 2)).reshape(a.shape)
+
+    a = run(p, rho, u, 40)
+    b = run(p, roll(rho), roll(u), 40)
+    for k in ("rho", "u", "pineq"):
+        assert np.array_equal(roll(a[k]), b[k]), k
+
+
+def test_init_then_moments_roundtrip():
+    shape = (72, 10, 9)
+    rho, u = inputs.taylor_green_3d(*shape, 0.02)
+    p = make_params(lattice=19, shape=shape, tau=0.6)
+    got = run(p, rho, u, 0)
+    assert np.abs(got["rho"] - rho).max() < 1e-7
+    assert max_rel(got["u"], u) < 1e-6
+    assert np.abs(got["pineq"]).max() < 1e-7
+
+
+def test_step_count_and_nonfinite_input():
+    p = make_params(lattice=19, shape=(16, 4, 4))
+    with Simulation(p) as sim:
+        rho = np.ones(256)
+        u = np.zeros((3, 256))
+        sim.init(rho, u)
+        sim.step(7)
+        sim.synchronize()
+        assert lb.lb_step_count(sim.handle) == 7
+        rho[5] = np.nan
+        with pytest.raises(lb.LbError) as e:
+            sim.init(rho, u)
+        assert e.value.status == lb.LB_ENONFINITE
+
+
+def _cone(field, shape, centre, h):
+    """Periodic (2h+1)^3 block of a flat field around centre."""
+    nx, ny, nz = shape
+    D = field.shape[0] if field.ndim == 2 else None
+    idx = [np.arange(c - h, c + h + 1) % n for c, n in zip(centre, shape)]
+    f3 = field.reshape((-1, nz, ny, nx)) if D else field.reshape((nz, ny, nx))
+    if D:
+        blk = f3[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+        return blk.reshape(D, -1)
+    return f3[idx[2]][:, idx[1]][:, :, idx[0]].reshape(-1)
+
+
+def test_full_size_512_sampled_against_oracle():
+    """The benchmark configuration (D3Q19, 512^3, periodic Taylor-Green,
+    tau 0.55, FP32): after 8 steps, sampled nodes -- at wavefront-segment and
+    domain edges -- match the oracle run on each sample's dependency cone."""
+    n, steps, tau = 512, 8, 0.55
+    shape = (n, n, n)
+    rho, u = inputs.taylor_green_3d(n, n, n, 0.02)
+    p = make_params(lattice=19, shape=shape, tau=tau)
+    got = run(p, rho, u, steps, pineq=False)
+    h = steps + 2
+    samples = [(0, 0, 0), (511, 511, 511), (255, 256, 17), (256, 3, 500), (63, 64, 65),
+               (64, 300, 255), (1, 510, 2)]
+    worst = 0.0
+    for (x, y, z) in samples:
+        sub_rho = _cone(rho, shape, (x, y, z), h)
+        sub_u = _cone(u, shape, (x, y, z), h)
+        q = oracle.Params(lattice=19, nx=2 * h + 1, ny=2 * h + 1, nz=2 * h + 1, tau=tau)
+        ref = oracle.simulate(q, sub_rho, sub_u, steps)
+        c = h + (2 * h + 1) * (h + (2 * h + 1) * h)
+        nidx = x + n * (y + n * z)
+        du = np.abs(got["u"][:, nidx] - ref["u"][:, c]).max()
+        worst = max(worst, du / 0.02)
+        assert abs(got["rho"][nidx] - ref["rho"][c]) < 1e-7
+    print(f"512^3 sampled: max |du|/u0 = {worst:.3e}")
+    assert worst <= FP32_TOL
+    assert np.isfinite(got["u"]).all()
