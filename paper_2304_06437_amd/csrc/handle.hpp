@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kernels2.hpp"
 #include "lb.h"
 
 namespace lbk {
@@ -38,6 +39,8 @@ struct lb_handle {
   int v2 = 1;  // nodes per lane of the stream-collide sweep
   lbk::StepParams<float> p32;
   lbk::StepParams<double> p64;
+  lbk::ColourParams<float> cp32;
+  lbk::ColourParams<double> cp64;
   // per-kernel timing
   std::vector<hipEvent_t> ev;
   int64_t tcap = 0, tcount = 0;
@@ -61,6 +64,12 @@ template <>
 inline const StepParams<float>& params_of<float>(const lb_handle* h) { return h->p32; }
 template <>
 inline const StepParams<double>& params_of<double>(const lb_handle* h) { return h->p64; }
+template <typename C>
+inline const ColourParams<C>& colour_of(const lb_handle* h);
+template <>
+inline const ColourParams<float>& colour_of<float>(const lb_handle* h) { return h->cp32; }
+template <>
+inline const ColourParams<double>& colour_of<double>(const lb_handle* h) { return h->cp64; }
 
 template <class L, int ORDER, typename S, typename C, int V1, int V2MAX>
 struct ImplT {
@@ -71,12 +80,18 @@ struct ImplT {
                        dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
     return hipGetLastError();
   }
+  // V nodes per lane = H chunks of E nodes; E fills at most 16 bytes of the
+  // wider of the storage and compute types.
   template <int V>
   static hipError_t sc(const lb_handle* h) {
+    constexpr int EMAX = 16 / (int)(sizeof(S) > sizeof(C) ? sizeof(S) : sizeof(C));
+    constexpr int E = V < EMAX ? V : EMAX;
+    constexpr int HH = V / E;
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, V>), dim3((unsigned)((waves + 3) / 4)),
-                       dim3(256), 0, h->stream, (const C*)h->m, (S*)h->f, p);
+    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH>),
+                       dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, h->stream,
+                       (const C*)h->m, (S*)h->f, p);
     return hipGetLastError();
   }
   static hipError_t stream_collide(const lb_handle* h) {
@@ -126,14 +141,77 @@ inline const Impl* impl_for_storage(int storage) {
     case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, V2D>::get();
     case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, V2F>::get();
     case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, V2F>::get();
-    case LB_STORE_BF16S: return ImplT<L, ORDER, bf16s, float, 4, V2F>::get();
+    case LB_STORE_BF16S: return ImplT<L, ORDER, __bf16, float, 4, V2F>::get();
+  }
+  return nullptr;
+}
+
+// Two-species (colour-gradient) launchers: second-order Hermite terms only.
+template <class L, typename S, typename C, int V1, int V2MAX>
+struct ImplT2 {
+  static hipError_t moments(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    const int64_t threads = p.npad / V1;
+    hipLaunchKernelGGL((k_moments2<L, S, C, V1>), dim3((unsigned)((threads + 255) / 256)),
+                       dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
+    return hipGetLastError();
+  }
+  template <int E>
+  static hipError_t sc(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    const int64_t waves = p.nseg * p.ny * p.nz;
+    hipLaunchKernelGGL((k_stream_collide2<L, S, C, E>), dim3((unsigned)((waves + 3) / 4)),
+                       dim3(256), 0, h->stream, (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
+    return hipGetLastError();
+  }
+  static hipError_t stream_collide(const lb_handle* h) {
+    switch (h->v2) {
+      case 4:
+        if constexpr (V2MAX >= 4) return sc<4>(h);
+        break;
+      case 2:
+        return sc<2>(h);
+      case 1:
+        return sc<1>(h);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t init(const lb_handle* h, const double* stage, int64_t n0, int64_t cnt) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_init2<L, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                       h->stream, stage, n0, cnt, (S*)h->f, p);
+    return hipGetLastError();
+  }
+  static hipError_t readout(const lb_handle* h, double* out, int64_t n0, int64_t cnt) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_readout2<L, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                       h->stream, (const S*)h->f, out, n0, cnt, p);
+    return hipGetLastError();
+  }
+  static hipError_t conserved(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    hipLaunchKernelGGL((k_conserved2<L, S, C>), dim3(kRedBlocks), dim3(256), 0, h->stream,
+                       (const S*)h->f, h->partial, h->L.N, p);
+    return hipGetLastError();
+  }
+  static const Impl* get() {
+    static const Impl impl = {V1, V2MAX, &moments, &stream_collide, &init, &readout, &conserved};
+    return &impl;
+  }
+};
+
+template <class L>
+inline const Impl* impl2_for_storage(int storage) {
+  switch (storage) {
+    case LB_STORE_F64: return ImplT2<L, double, double, 2, 2>::get();
+    case LB_STORE_F32: return ImplT2<L, float, float, 4, 4>::get();
   }
   return nullptr;
 }
 
 // One translation unit per lattice instantiates its kernels.
-const Impl* impl_d2q9(int storage);
-const Impl* impl_d3q19(int storage);
+const Impl* impl_d2q9(int storage, int species);
+const Impl* impl_d3q19(int storage, int species);
 const Impl* impl_d3q27(int order, int storage);
 
 }  // namespace lbk

@@ -240,6 +240,8 @@ __device__ __forceinline__ float lane_from_below(float v) { return __shfl_up(v, 
 __device__ __forceinline__ float lane_from_above(float v) { return __shfl_down(v, 1, 64); }
 __device__ __forceinline__ double lane_from_below(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double lane_from_above(double v) { return __shfl_down(v, 1, 64); }
+__device__ __forceinline__ float lane_bcast(float v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ double lane_bcast(double v, int src) { return __shfl(v, src, 64); }
 
 // -------------------------------------------------------------------------
 // Sweep 1: moments.  Each lane handles V consecutive nodes of the flattened
@@ -254,6 +256,8 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
   C s[L::Q][V];
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
+  // keep every load in flight before the arithmetic starts
+  __builtin_amdgcn_sched_barrier(0);
   C out[ML::M][V];
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -270,24 +274,35 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 
 // -------------------------------------------------------------------------
 // Sweep 2: fused streaming + collision with boundaries.
+//
+// Lane mapping: a wavefront's segment of 64 V nodes (V = E H) is split into H
+// chunks of 64 E nodes; lane l owns nodes h*64E + l*E + e (e < E) of chunk h.
+// Every vector load or store instruction therefore covers 64 E contiguous
+// nodes (16 bytes per lane for E = 4 floats): whole cache lines per
+// instruction.
 // -------------------------------------------------------------------------
-template <class L, int ORDER, typename S, typename C, int V>
+template <class L, int ORDER, typename S, typename C, int E, int H>
 struct StreamCollide {
   using ML = MomentLayout<L>;
   using CL = CoefLayout<L, ORDER>;
   static constexpr int M = ML::M;
   static constexpr int K = CL::K;
+  static constexpr int W = 64 * E * H;  // nodes per segment
 
-  // Emit link A for this lane's V nodes.
+  struct Lane {
+    int64_t xh[H];    // first node of this lane's chunk h
+    bool act[H];      // chunk h inside the row
+    int64_t y, z, rowbase;
+  };
+
+  // Emit link A for this lane's nodes.
   template <int A>
   __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
-                                              const C (&own)[V][K], const C (&left)[K],
-                                              const C (&right)[K], int64_t xs, int64_t y,
-                                              int64_t z, int64_t rowbase) {
+                                              const C (&own)[H][E][K], const C (&left)[H][K],
+                                              const C (&right)[H][K], const Lane& ln) {
     constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
     constexpr int AB = opposite<L>(A);
-    // target row of the pushed values
-    int64_t ty = y + cy, tz = z + cz;
+    int64_t ty = ln.y + cy, tz = ln.z + cz;
     bool row_in = true;
     if (cy != 0) {
       if (ty < 0 || ty >= p.ny) {
@@ -301,61 +316,66 @@ struct StreamCollide {
         else tz = (tz < 0) ? p.nz - 1 : 0;
       }
     }
-    if (row_in) {
-      // value arriving at x (this lane's nodes) from source x - cx of this row
-      C val[V];
+    const int64_t trow = p.nx * (ty + p.ny * tz);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        if constexpr (cx == 0) {
-          val[e] = link_value<L, ORDER, A, C>(own[e]);
-        } else if constexpr (cx > 0) {
-          val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[e > 0 ? e - 1 : 0])
-                           : link_value<L, ORDER, A, C>(left);
+    for (int h = 0; h < H; ++h) {
+      if (!ln.act[h]) continue;
+      const int64_t xs = ln.xh[h];
+      if (row_in) {
+        // value arriving at x (this lane's nodes) from source x - cx of this row
+        C val[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if constexpr (cx == 0) {
+            val[e] = link_value<L, ORDER, A, C>(own[h][e]);
+          } else if constexpr (cx > 0) {
+            val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[h][e > 0 ? e - 1 : 0])
+                             : link_value<L, ORDER, A, C>(left[h]);
+          } else {
+            val[e] = (e < E - 1) ? link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0])
+                                 : link_value<L, ORDER, A, C>(right[h]);
+          }
+        }
+        S* dst = f + (int64_t)A * p.npad + trow + xs;
+        const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
+        const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);    // source x = nx
+        if (!(cut_lo || cut_hi)) {
+          store_pack<S, C, E>(dst, val);
         } else {
-          val[e] = (e < V - 1) ? link_value<L, ORDER, A, C>(own[e < V - 1 ? e + 1 : 0])
-                               : link_value<L, ORDER, A, C>(right);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if ((cut_lo && e == 0) || (cut_hi && e == E - 1)) continue;
+            dst[e] = Codec<S, C>::store(val[e]);
+          }
         }
-      }
-      S* dst = f + (int64_t)A * p.npad + p.nx * (ty + p.ny * tz) + xs;
-      const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
-      const bool cut_hi = (cx < 0) && p.bbx && (xs + V == p.nx);    // source x = nx
-      if (!(cut_lo || cut_hi)) {
-        store_pack<S, C, V>(dst, val);
       } else {
+        // every node of this row sends link A across a y/z wall: it comes
+        // back into the same node as the opposite link
+        C bv[E];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          if ((cut_lo && e == 0) || (cut_hi && e == V - 1)) continue;
-          dst[e] = Codec<S, C>::store(val[e]);
-        }
+        for (int e = 0; e < E; ++e) bv[e] = link_value<L, ORDER, A, C>(own[h][e]);
+        store_pack<S, C, E>(f + (int64_t)AB * p.npad + ln.rowbase + xs, bv);
       }
-    } else {
-      // every node of this row sends link A across a y/z wall: it comes back
-      // into the same node as the opposite link
-      C bv[V];
-#pragma unroll
-      for (int e = 0; e < V; ++e) bv[e] = link_value<L, ORDER, A, C>(own[e]);
-      store_pack<S, C, V>(f + (int64_t)AB * p.npad + rowbase + xs, bv);
-    }
-    if constexpr (cx != 0) {
-      if (row_in && p.bbx) {
-        if (cx > 0 && xs + V == p.nx)
-          f[(int64_t)AB * p.npad + rowbase + p.nx - 1] =
-              Codec<S, C>::store(link_value<L, ORDER, A, C>(own[V - 1]));
-        if (cx < 0 && xs == 0)
-          f[(int64_t)AB * p.npad + rowbase] =
-              Codec<S, C>::store(link_value<L, ORDER, A, C>(own[0]));
+      if constexpr (cx != 0) {
+        if (row_in && p.bbx) {
+          if (cx > 0 && xs + E == p.nx)
+            f[(int64_t)AB * p.npad + ln.rowbase + p.nx - 1] =
+                Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][E - 1]));
+          if (cx < 0 && xs == 0)
+            f[(int64_t)AB * p.npad + ln.rowbase] =
+                Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][0]));
+        }
       }
     }
   }
 
   template <int A>
   __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
-                                               const C (&own)[V][K], const C (&left)[K],
-                                               const C (&right)[K], int64_t xs, int64_t y,
-                                               int64_t z, int64_t rowbase) {
+                                               const C (&own)[H][E][K], const C (&left)[H][K],
+                                               const C (&right)[H][K], const Lane& ln) {
     if constexpr (A < L::Q) {
-      link<A>(f, p, own, left, right, xs, y, z, rowbase);
-      links<A + 1>(f, p, own, left, right, xs, y, z, rowbase);
+      link<A>(f, p, own, left, right, ln);
+      links<A + 1>(f, p, own, left, right, ln);
     }
   }
 
@@ -374,38 +394,67 @@ struct StreamCollide {
     if (wave >= p.nseg * rows) return;  // whole wavefront leaves together
     const int64_t seg = wave % p.nseg;
     const int64_t row = wave / p.nseg;
-    const int64_t y = row % p.ny;
-    const int64_t z = row / p.ny;
-    const int64_t x0 = seg * (64 * V);
-    const int64_t xs = x0 + (int64_t)lane * V;
-    const int64_t xend = (x0 + 64 * V < p.nx) ? x0 + 64 * V : p.nx;
-    const bool active = xs < p.nx;
-    const int64_t rowbase = p.nx * row;
-
-    C own[V][K];
-    if (active) {
-      C mv[M][V];
+    Lane ln;
+    ln.y = row % p.ny;
+    ln.z = row / p.ny;
+    ln.rowbase = p.nx * row;
+    const int64_t x0 = seg * W;
+    const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
 #pragma unroll
-      for (int q = 0; q < M; ++q) load_plain<C, V>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        C mm[M];
-#pragma unroll
-        for (int q = 0; q < M; ++q) mm[q] = mv[q][e];
-        post_collision<L, ORDER, C>(mm, p, own[e]);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < V; ++e)
-#pragma unroll
-        for (int q = 0; q < K; ++q) own[e][q] = C(0);
+    for (int h = 0; h < H; ++h) {
+      ln.xh[h] = x0 + (int64_t)h * 64 * E + (int64_t)lane * E;
+      ln.act[h] = ln.xh[h] < p.nx;
     }
-    // x-neighbours of the lane's first and last node
-    C left[K], right[K];
+
+    C own[H][E][K];
+    {
+      C mv[H][M][E];
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      left[q] = lane_from_below(own[V - 1][q]);
-      right[q] = lane_from_above(own[0][q]);
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+          if (ln.act[h]) {
+            load_plain<C, E>(m + (int64_t)q * p.npad + ln.rowbase + ln.xh[h], mv[h][q]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) mv[h][q][e] = C(0);
+          }
+        }
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          C mm[M];
+#pragma unroll
+          for (int q = 0; q < M; ++q) mm[q] = mv[h][q][e];
+          post_collision<L, ORDER, C>(mm, p, own[h][e]);
+        }
+    }
+    // x-neighbours of each chunk's first and last node
+    C left[H][K], right[H][K];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        left[h][q] = lane_from_below(own[h][E - 1][q]);
+        right[h][q] = lane_from_above(own[h][0][q]);
+      }
+    if constexpr (H > 1) {
+      // chunk boundaries inside the segment: lane 0 of chunk h follows lane
+      // 63 of chunk h-1
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if (h > 0) {
+            const C v = lane_bcast(own[h - 1][E - 1][q], 63);
+            if (lane == 0) left[h][q] = v;
+          }
+          if (h < H - 1) {
+            const C v = lane_bcast(own[h + 1][0][q], 0);
+            if (lane == 63) right[h][q] = v;
+          }
+        }
     }
     if (lane == 0) {
       int64_t xl = x0 - 1;
@@ -414,26 +463,28 @@ struct StreamCollide {
         if (p.bbx) ok = false;
         else xl = p.nx - 1;
       }
-      if (ok) load_coef(m, p, rowbase + xl, left);
+      if (ok) load_coef(m, p, ln.rowbase + xl, left[0]);
     }
-    if (active && xs + V == xend) {
-      int64_t xr = xend;
-      bool ok = true;
-      if (xr >= p.nx) {
-        if (p.bbx) ok = false;
-        else xr = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      if (ln.act[h] && ln.xh[h] + E == xend) {
+        int64_t xr = xend;
+        bool ok = true;
+        if (xr >= p.nx) {
+          if (p.bbx) ok = false;
+          else xr = 0;
+        }
+        if (ok) load_coef(m, p, ln.rowbase + xr, right[h]);
       }
-      if (ok) load_coef(m, p, rowbase + xr, right);
     }
-    if (!active) return;
-    links<0>(f, p, own, left, right, xs, y, z, rowbase);
+    links<0>(f, p, own, left, right, ln);
   }
 };
 
-template <class L, int ORDER, typename S, typename C, int V>
+template <class L, int ORDER, typename S, typename C, int E, int H>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  StreamCollide<L, ORDER, S, C, V>::run(m, f, p);
+  StreamCollide<L, ORDER, S, C, E, H>::run(m, f, p);
 }
 
 // -------------------------------------------------------------------------

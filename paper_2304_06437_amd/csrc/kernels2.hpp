@@ -1,0 +1,592 @@
+// Two-species colour-gradient kernels (Section 2.1), D2Q9 and D3Q19.
+//
+// The mixture g = f_R + f_B is relaxed with the regularized collision of
+// kernels.hpp (one set of moments for the mixture), perturbed by
+//   Omega1_a = (9/4) sigma omega |G| ( t_a (c_a.n)^2 - B_a ),  n = G/|G|,
+// and recoloured (Latva-Kokko):
+//   f_R,a = (rho_R/rho) g*_a + beta (rho_R rho_B / rho) t_a cos(theta_a),
+//   f_B,a = g*_a - f_R,a,  cos(theta_a) = c_a.n / |c_a|,
+// where G = grad phi, phi = (rho_R - rho_B)/rho, from the isotropic stencil
+// G = (1/cs2) sum_b t_b c_b phi(x + c_b) (neighbours beyond a wall take the
+// node's own phi).  No perturbation and cos(theta) = 0 where |G|^2 <= 1e-20.
+//
+// Storage: set 0 holds the mixture shifted, g_a - t_a rho0 (so its velocity
+// keeps full precision), set 1 the red populations f_R,a unshifted.  The
+// moments sweep writes drho, j, Pi^neq and phi (M + 1 arrays).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbk {
+
+template <class L>
+struct ColourWeights;
+
+// Reis & Phillips (2007) set for D2Q9.
+template <>
+struct ColourWeights<D2Q9> {
+  static constexpr double B[9] = {-4.0 / 27.0,  2.0 / 27.0,  2.0 / 27.0,  2.0 / 27.0, 2.0 / 27.0,
+                                  5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0};
+};
+
+// Liu, Valocchi & Kang (2012) set for D3Q19.
+template <>
+struct ColourWeights<D3Q19> {
+  static constexpr double B[19] = {-1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                   1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+};
+
+template <typename C>
+struct ColourParams {
+  C pert;   // (9/4) sigma omega
+  C beta;
+};
+
+// Per-node state carried along x in the two-species sweep:
+// post-collision coefficients of the mixture, then S = (9/4) sigma omega |G|,
+// the unit normal n (D), rho_R/rho and beta rho_R rho_B / rho.
+template <class L>
+struct ColourLayout {
+  static constexpr int K = CoefLayout<L, 2>::K;
+  static constexpr int S = K;
+  static constexpr int N = K + 1;
+  static constexpr int XR = K + 1 + L::D;
+  static constexpr int RB = K + 2 + L::D;
+  static constexpr int KT = K + 3 + L::D;
+};
+
+// Moments sweep: mixture moments from set 0, red density from set 1, and
+// phi = (2 rho_R - rho)/rho.
+template <class L, typename S, typename C, int V>
+__global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __restrict__ m,
+                                                  StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (i0 >= p.npad) return;
+  C s[L::Q][V];
+  C rr[V];
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
+#pragma unroll
+  for (int e = 0; e < V; ++e) rr[e] = C(0);
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) {
+    C r[V];
+    load_pack<S, C, V>(f + (int64_t)(L::Q + a) * p.npad + i0, r);
+#pragma unroll
+    for (int e = 0; e < V; ++e) rr[e] += r[e];
+  }
+  C out[ML::M + 1][V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    C se[L::Q], me[ML::M];
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) se[a] = s[a][e];
+    node_moments<L, C>(se, p, me);
+#pragma unroll
+    for (int q = 0; q < ML::M; ++q) out[q][e] = me[q];
+    const C rho = p.rho0 + me[ML::RHO];
+    out[ML::M][e] = (C(2) * rr[e] - rho) / rho;
+  }
+#pragma unroll
+  for (int q = 0; q <= ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+}
+
+// Phase field of node (x + dx, ty, tz) given the wrapped/validated row
+// (ty, tz): x wraps for periodic x; beyond an x wall the node's own phi.
+template <typename C>
+__device__ __forceinline__ C phi_at(const C* __restrict__ phi, const StepParams<C>& p,
+                                    int64_t trow_base, int64_t x, int dx, C own) {
+  int64_t xx = x + dx;
+  if (xx < 0 || xx >= p.nx) {
+    if (p.bbx) return own;
+    xx = (xx < 0) ? p.nx - 1 : 0;
+  }
+  return phi[trow_base + xx];
+}
+
+// Full per-node state of node (x, y, z) by scalar loads (segment halos).
+template <class L, typename C>
+__device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>& p,
+                                    const ColourParams<C>& cp, int64_t x, int64_t y, int64_t z,
+                                    C (&st)[ColourLayout<L>::KT]) {
+  using ML = MomentLayout<L>;
+  using XL = ColourLayout<L>;
+  constexpr int D = L::D;
+  const int64_t n = x + p.nx * (y + p.ny * z);
+  C mm[ML::M];
+#pragma unroll
+  for (int q = 0; q < ML::M; ++q) mm[q] = m[(int64_t)q * p.npad + n];
+  C k[XL::K];
+  post_collision<L, 2, C>(mm, p, k);
+#pragma unroll
+  for (int q = 0; q < XL::K; ++q) st[q] = k[q];
+  const C* phi = m + (int64_t)ML::M * p.npad;
+  const C own = phi[n];
+  // same row-by-row summation order as the vector path in StreamCollide2
+  C G[3] = {C(0), C(0), C(0)};
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      bool has[3] = {false, false, false};
+      int wm[3] = {0, 0, 0};
+#pragma unroll
+      for (int b = 1; b < L::Q; ++b)
+        if (L::c[b][1] == dy && L::c[b][2] == dz) {
+          has[L::c[b][0] + 1] = true;
+          wm[L::c[b][0] + 1] = L::wmul[b];
+        }
+      if (!(has[0] || has[1] || has[2])) continue;
+      int64_t ty = y + dy, tz = z + dz;
+      bool inside = true;
+      if (ty < 0 || ty >= p.ny) {
+        if (p.bby) inside = false;
+        else ty = (ty < 0) ? p.ny - 1 : 0;
+      }
+      if (tz < 0 || tz >= p.nz) {
+        if (p.bbz) inside = false;
+        else tz = (tz < 0) ? p.nz - 1 : 0;
+      }
+      const int64_t tb = p.nx * (ty + p.ny * tz);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!has[dx + 1]) continue;
+        const C v = inside ? phi_at<C>(phi, p, tb, x, dx, own) : own;
+        const C wv = C(wm[dx + 1]) * v;
+        if (dx > 0) G[0] += wv;
+        if (dx < 0) G[0] -= wv;
+        if (dy > 0) G[1] += wv;
+        if (dy < 0) G[1] -= wv;
+        if (D == 3) {
+          if (dz > 0) G[2] += wv;
+          if (dz < 0) G[2] -= wv;
+        }
+      }
+    }
+  const C rho = p.rho0 + mm[ML::RHO];
+  const C xr = (C(1) + own) * C(0.5);
+  const C xb = (C(1) - own) * C(0.5);
+  // G = (1/cs2) sum t_b c_b phi = (3/wden) sum wmul_b c_b phi
+  C G2 = C(0);
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    G[al] = scaled<3, L::wden>(G[al]);
+    G2 += G[al] * G[al];
+  }
+  if (G2 > C(1e-20)) {
+    const C Gn = sqrt(G2);
+    st[XL::S] = cp.pert * Gn;
+#pragma unroll
+    for (int al = 0; al < D; ++al) st[XL::N + al] = G[al] / Gn;
+  } else {
+    st[XL::S] = C(0);
+#pragma unroll
+    for (int al = 0; al < D; ++al) st[XL::N + al] = C(0);
+  }
+  st[XL::XR] = xr;
+  st[XL::RB] = cp.beta * xr * xb * rho;
+}
+
+// Value of link A from a source node's state: (shifted mixture, red).
+template <class L, int A, typename C>
+__device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], const C rho0,
+                                            C& gs, C& fr) {
+  using XL = ColourLayout<L>;
+  constexpr int D = L::D;
+  const C (&k)[XL::K] = *reinterpret_cast<const C(*)[XL::K]>(&st[0]);
+  C g = link_value<L, 2, A, C>(k);
+  C cn = C(0);
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    if (L::c[A][al] > 0) cn += st[XL::N + al];
+    if (L::c[A][al] < 0) cn -= st[XL::N + al];
+  }
+  constexpr double t = L::w[A];
+  constexpr double Bw = ColourWeights<L>::B[A];
+  constexpr int c2 = L::c[A][0] * L::c[A][0] + L::c[A][1] * L::c[A][1] + L::c[A][2] * L::c[A][2];
+  g += st[XL::S] * (C(t) * cn * cn - C(Bw));
+  const C gtot = g + C(t) * rho0;
+  C rec = C(0);
+  if constexpr (c2 > 0) {
+    constexpr double inv = c2 == 1 ? 1.0 : c2 == 2 ? 0.70710678118654752440 : 0.57735026918962576451;
+    rec = st[XL::RB] * C(t) * cn * C(inv);
+  }
+  gs = g;
+  fr = st[XL::XR] * gtot + rec;
+}
+
+// Stream-collide for two species.  One wavefront per x-row segment of 64 E
+// nodes (E per lane), as in StreamCollide; the phase-field gradient reads
+// phi from the 3 (2D) or 9 (3D) rows around the source row.
+template <class L, typename S, typename C, int E>
+struct StreamCollide2 {
+  using ML = MomentLayout<L>;
+  using XL = ColourLayout<L>;
+  static constexpr int M = ML::M;
+  static constexpr int KT = XL::KT;
+  static constexpr int W = 64 * E;
+
+  template <int A>
+  __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
+                                              const C (&own)[E][KT], const C (&left)[KT],
+                                              const C (&right)[KT], int64_t xs, int64_t y,
+                                              int64_t z, int64_t rowbase) {
+    constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
+    constexpr int AB = opposite<L>(A);
+    int64_t ty = y + cy, tz = z + cz;
+    bool row_in = true;
+    if (cy != 0 && (ty < 0 || ty >= p.ny)) {
+      if (p.bby) row_in = false;
+      else ty = (ty < 0) ? p.ny - 1 : 0;
+    }
+    if (cz != 0 && (tz < 0 || tz >= p.nz)) {
+      if (p.bbz) row_in = false;
+      else tz = (tz < 0) ? p.nz - 1 : 0;
+    }
+    S* fr0 = f + (int64_t)A * p.npad;
+    S* fr1 = f + (int64_t)(L::Q + A) * p.npad;
+    if (row_in) {
+      C gv[E], rv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if constexpr (cx == 0) {
+          colour_link<L, A, C>(own[e], p.rho0, gv[e], rv[e]);
+        } else if constexpr (cx > 0) {
+          if (e > 0) colour_link<L, A, C>(own[e > 0 ? e - 1 : 0], p.rho0, gv[e], rv[e]);
+          else colour_link<L, A, C>(left, p.rho0, gv[e], rv[e]);
+        } else {
+          if (e < E - 1) colour_link<L, A, C>(own[e < E - 1 ? e + 1 : 0], p.rho0, gv[e], rv[e]);
+          else colour_link<L, A, C>(right, p.rho0, gv[e], rv[e]);
+        }
+      }
+      const int64_t t = p.nx * (ty + p.ny * tz) + xs;
+      const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);
+      const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);
+      if (!(cut_lo || cut_hi)) {
+        store_pack<S, C, E>(fr0 + t, gv);
+        store_pack<S, C, E>(fr1 + t, rv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if ((cut_lo && e == 0) || (cut_hi && e == E - 1)) continue;
+          fr0[t + e] = Codec<S, C>::store(gv[e]);
+          fr1[t + e] = Codec<S, C>::store(rv[e]);
+        }
+      }
+    } else {
+      C gv[E], rv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], p.rho0, gv[e], rv[e]);
+      store_pack<S, C, E>(f + (int64_t)AB * p.npad + rowbase + xs, gv);
+      store_pack<S, C, E>(f + (int64_t)(L::Q + AB) * p.npad + rowbase + xs, rv);
+    }
+    if constexpr (cx != 0) {
+      if (row_in && p.bbx) {
+        int e = -1;
+        int64_t xw = -1;
+        if (cx > 0 && xs + E == p.nx) { e = E - 1; xw = p.nx - 1; }
+        if (cx < 0 && xs == 0) { e = 0; xw = 0; }
+        if (e >= 0) {
+          C g, r;
+          if (e == 0) colour_link<L, A, C>(own[0], p.rho0, g, r);
+          else colour_link<L, A, C>(own[E - 1], p.rho0, g, r);
+          f[(int64_t)AB * p.npad + rowbase + xw] = Codec<S, C>::store(g);
+          f[(int64_t)(L::Q + AB) * p.npad + rowbase + xw] = Codec<S, C>::store(r);
+        }
+      }
+    }
+  }
+
+  template <int A>
+  __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
+                                               const C (&own)[E][KT], const C (&left)[KT],
+                                               const C (&right)[KT], int64_t xs, int64_t y,
+                                               int64_t z, int64_t rowbase) {
+    if constexpr (A < L::Q) {
+      link<A>(f, p, own, left, right, xs, y, z, rowbase);
+      links<A + 1>(f, p, own, left, right, xs, y, z, rowbase);
+    }
+  }
+
+  __device__ static void run(const C* __restrict__ m, S* __restrict__ f, const StepParams<C>& p,
+                             const ColourParams<C>& cp) {
+    constexpr int D = L::D;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t rows = p.ny * p.nz;
+    if (wave >= p.nseg * rows) return;
+    const int64_t seg = wave % p.nseg;
+    const int64_t row = wave / p.nseg;
+    const int64_t y = row % p.ny, z = row / p.ny;
+    const int64_t rowbase = p.nx * row;
+    const int64_t x0 = seg * W;
+    const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
+    const int64_t xs = x0 + (int64_t)lane * E;
+    const bool act = xs < p.nx;
+    const C* phi = m + (int64_t)M * p.npad;
+
+    C own[E][KT];
+    C phio[E];
+    {
+      C mv[M][E];
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (act) load_plain<C, E>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
+        else
+#pragma unroll
+          for (int e = 0; e < E; ++e) mv[q][e] = C(0);
+      }
+      if (act) load_plain<C, E>(phi + rowbase + xs, phio);
+      else
+#pragma unroll
+        for (int e = 0; e < E; ++e) phio[e] = C(0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        C mm[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) mm[q] = mv[q][e];
+        C k[XL::K];
+        post_collision<L, 2, C>(mm, p, k);
+#pragma unroll
+        for (int q = 0; q < XL::K; ++q) own[e][q] = k[q];
+        const C rho = p.rho0 + mm[ML::RHO];
+        const C xr = (C(1) + phio[e]) * C(0.5);
+        const C xb = (C(1) - phio[e]) * C(0.5);
+        own[e][XL::XR] = xr;
+        own[e][XL::RB] = cp.beta * xr * xb * rho;
+      }
+    }
+    // phase-field gradient of this lane's nodes from the rows around it
+    C G[E][3];
+#pragma unroll
+    for (int e = 0; e < E; ++e) G[e][0] = G[e][1] = G[e][2] = C(0);
+#pragma unroll
+    for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        // links of the stencil reaching row (y + dy, z + dz): c_bx in {-1,0,1}
+        bool has[3] = {false, false, false};
+        int wm[3] = {0, 0, 0};
+#pragma unroll
+        for (int b = 1; b < L::Q; ++b)
+          if (L::c[b][1] == dy && L::c[b][2] == dz) {
+            has[L::c[b][0] + 1] = true;
+            wm[L::c[b][0] + 1] = L::wmul[b];
+          }
+        if (!(has[0] || has[1] || has[2])) continue;
+        int64_t ty = y + dy, tz = z + dz;
+        bool inside = true;
+        if (ty < 0 || ty >= p.ny) {
+          if (p.bby) inside = false;
+          else ty = (ty < 0) ? p.ny - 1 : 0;
+        }
+        if (tz < 0 || tz >= p.nz) {
+          if (p.bbz) inside = false;
+          else tz = (tz < 0) ? p.nz - 1 : 0;
+        }
+        const int64_t tb = p.nx * (ty + p.ny * tz);
+        C pv[E];
+        if (inside) {
+          if (act) load_plain<C, E>(phi + tb + xs, pv);
+          else
+#pragma unroll
+            for (int e = 0; e < E; ++e) pv[e] = C(0);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) pv[e] = phio[e];
+        }
+        // x-neighbours of the lane's first and last node in this row
+        C pl = lane_from_below(pv[E - 1]);
+        C pr = lane_from_above(pv[0]);
+        if (inside) {
+          if (lane == 0) pl = phi_at<C>(phi, p, tb, x0, -1, phio[0]);
+          if (act && xs + E == xend) pr = phi_at<C>(phi, p, tb, xend - 1, 1, phio[E - 1]);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          C vals[3];
+          vals[1] = pv[e];
+          vals[0] = (e > 0) ? pv[e > 0 ? e - 1 : 0] : pl;
+          vals[2] = (e < E - 1) ? pv[e < E - 1 ? e + 1 : 0] : pr;
+          if (!inside) {
+            // the row lies beyond a y/z wall: every neighbour takes the own value
+            vals[0] = vals[1] = vals[2] = phio[e];
+          } else if (p.bbx) {
+            // x walls: neighbours beyond x = 0 / nx - 1 take the own value
+            if (xs + e == 0) vals[0] = phio[e];
+            if (xs + e == p.nx - 1) vals[2] = phio[e];
+          }
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!has[dx + 1]) continue;
+            const C wv = C(wm[dx + 1]) * vals[dx + 1];
+            if (dx > 0) G[e][0] += wv;
+            if (dx < 0) G[e][0] -= wv;
+            if (dy > 0) G[e][1] += wv;
+            if (dy < 0) G[e][1] -= wv;
+            if (D == 3) {
+              if (dz > 0) G[e][2] += wv;
+              if (dz < 0) G[e][2] -= wv;
+            }
+          }
+        }
+      }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      C G2 = C(0);
+#pragma unroll
+      for (int al = 0; al < D; ++al) {
+        G[e][al] = scaled<3, L::wden>(G[e][al]);
+        G2 += G[e][al] * G[e][al];
+      }
+      if (G2 > C(1e-20)) {
+        const C Gn = sqrt(G2);
+        own[e][XL::S] = cp.pert * Gn;
+#pragma unroll
+        for (int al = 0; al < D; ++al) own[e][XL::N + al] = G[e][al] / Gn;
+      } else {
+        own[e][XL::S] = C(0);
+#pragma unroll
+        for (int al = 0; al < D; ++al) own[e][XL::N + al] = C(0);
+      }
+    }
+    C left[KT], right[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+      left[q] = lane_from_below(own[E - 1][q]);
+      right[q] = lane_from_above(own[0][q]);
+    }
+    if (lane == 0) {
+      int64_t xl = x0 - 1;
+      bool ok = true;
+      if (xl < 0) {
+        if (p.bbx) ok = false;
+        else xl = p.nx - 1;
+      }
+      if (ok) colour_state_scalar<L, C>(m, p, cp, xl, y, z, left);
+    }
+    if (act && xs + E == xend) {
+      int64_t xr = xend;
+      bool ok = true;
+      if (xr >= p.nx) {
+        if (p.bbx) ok = false;
+        else xr = 0;
+      }
+      if (ok) colour_state_scalar<L, C>(m, p, cp, xr, y, z, right);
+    }
+    if (!act) return;
+    links<0>(f, p, own, left, right, xs, y, z, rowbase);
+  }
+};
+
+template <class L, typename S, typename C, int E>
+__global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m,
+                                                         S* __restrict__ f, StepParams<C> p,
+                                                         ColourParams<C> cp) {
+  StreamCollide2<L, S, C, E>::run(m, f, p, cp);
+}
+
+// Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.
+// stage: (2 + D) x cnt doubles: drho, u, phi.
+template <class L, typename S, typename C, int A>
+__device__ __forceinline__ void init2_links(S* __restrict__ f, int64_t npad, int64_t n,
+                                            const C (&k)[CoefLayout<L, 2>::K], C rho0, C xr) {
+  if constexpr (A < L::Q) {
+    const C s = link_value<L, 2, A, C>(k);
+    f[(int64_t)A * npad + n] = Codec<S, C>::store(s);
+    f[(int64_t)(L::Q + A) * npad + n] = Codec<S, C>::store(xr * (s + C(L::w[A]) * rho0));
+    init2_links<L, S, C, A + 1>(f, npad, n, k, rho0, xr);
+  }
+}
+
+template <class L, typename S, typename C>
+__global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage, int64_t n0,
+                                               int64_t cnt, S* __restrict__ f, StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  C mm[ML::M];
+#pragma unroll
+  for (int q = 0; q < ML::M; ++q) mm[q] = C(0);
+  mm[ML::RHO] = (C)stage[i];
+#pragma unroll
+  for (int al = 0; al < L::D; ++al) mm[ML::J + al] = p.rho0 * (C)stage[(int64_t)(1 + al) * cnt + i];
+  const C xr = (C(1) + (C)stage[(int64_t)(1 + L::D) * cnt + i]) * C(0.5);
+  StepParams<C> q = p;
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    q.F[al] = C(0);
+    q.halfF[al] = C(0);
+  }
+  C k[CoefLayout<L, 2>::K];
+  post_collision<L, 2, C>(mm, q, k);
+  init2_links<L, S, C, 0>(f, p.npad, n0 + i, k, p.rho0, xr);
+}
+
+// Read-out: rho, u, Pi^neq of the mixture and phi; (2 + D + D(D+1)/2) x cnt.
+template <class L, typename S, typename C>
+__global__ __launch_bounds__(256) void k_readout2(const S* __restrict__ f, double* __restrict__ out,
+                                                  int64_t n0, int64_t cnt, StepParams<C> p) {
+  using ML = MomentLayout<L>;
+  constexpr int D = L::D;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t n = n0 + i;
+  C s[L::Q], me[ML::M];
+  C rr = C(0);
+#pragma unroll
+  for (int a = 0; a < L::Q; ++a) {
+    s[a] = Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+    rr += Codec<S, C>::load(f[(int64_t)(L::Q + a) * p.npad + n]);
+  }
+  node_moments<L, C>(s, p, me);
+  const C rho = p.rho0 + me[ML::RHO];
+  out[i] = (double)p.rho0 + (double)me[ML::RHO];
+#pragma unroll
+  for (int al = 0; al < D; ++al)
+    out[(int64_t)(1 + al) * cnt + i] = (double)((me[ML::J + al] + p.halfF[al]) * p.inv_rho0);
+#pragma unroll
+  for (int q = 0; q < D * (D + 1) / 2; ++q)
+    out[(int64_t)(1 + D + q) * cnt + i] = (double)me[ML::PID + q];
+  out[(int64_t)(1 + D + D * (D + 1) / 2) * cnt + i] = (double)((C(2) * rr - rho) / rho);
+}
+
+// FP64 reductions: drho, j (3), red mass.
+template <class L, typename S, typename C>
+__global__ __launch_bounds__(256) void k_conserved2(const S* __restrict__ f,
+                                                    double* __restrict__ partial, int64_t N,
+                                                    StepParams<C> p) {
+  __shared__ double red[5][256];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+#pragma unroll
+    for (int a = 0; a < L::Q; ++a) {
+      const double s = (double)Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+      acc[0] += s;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        if (L::c[a][al] > 0) acc[1 + al] += s;
+        if (L::c[a][al] < 0) acc[1 + al] -= s;
+      }
+      acc[4] += (double)Codec<S, C>::load(f[(int64_t)(L::Q + a) * p.npad + n]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) partial[(int64_t)blockIdx.x * 8 + q] = red[q][0];
+}
+
+}  // namespace lbk

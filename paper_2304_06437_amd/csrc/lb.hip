@@ -1,8 +1,9 @@
 // Host side of liblb.so: the C ABI declared in include/lb.h.
 //
 // Device memory of one simulation (lb_required_bytes):
-//   f  species*Q population arrays, storage type, shifted (f_a - t_a rho0)
-//   m  M moment arrays (drho, j, Pi^neq), compute type
+//   f  species*Q population arrays, storage type: f_a - t_a rho0 (one
+//      species), or the mixture g_a - t_a rho0 and the red f_R,a (two)
+//   m  M moment arrays (drho, j, Pi^neq, and phi for two species), compute type
 //   r  FP64 partial sums of the conservation reduction
 // Every array holds npad >= N elements (npad a multiple of 4096), so every
 // array starts 256-byte aligned and the moments sweep needs no tail.
@@ -77,8 +78,9 @@ int validate(const lb_params* p) {
   if (p->species == 2) {
     if (!(std::isfinite(p->sigma) && p->sigma >= 0.0)) return LB_EINVAL;
     if (!(std::isfinite(p->beta) && p->beta >= 0.0 && p->beta <= 1.0)) return LB_EINVAL;
-    if (p->lattice == LB_D3Q27) return LB_EINVAL;  // no published B_a set used here
-    return LB_EUNSUPPORTED;
+    if (p->lattice == LB_D3Q27) return LB_EINVAL;  // no colour weights B_a for D3Q27 here
+    if (p->hermite_order != 2) return LB_EINVAL;
+    if (p->storage != LB_STORE_F32 && p->storage != LB_STORE_F64) return LB_EUNSUPPORTED;
   }
   const bool f64 = p->compute == LB_COMPUTE_F64;
   const bool f32 = p->compute == LB_COMPUTE_F32;
@@ -105,7 +107,7 @@ Layout layout_of(const lb_params* p) {
   Layout L;
   L.Q = lattice_q(p->lattice);
   L.D = p->lattice == LB_D2Q9 ? 2 : 3;
-  L.M = 1 + L.D + L.D * (L.D + 1) / 2;
+  L.M = 1 + L.D + L.D * (L.D + 1) / 2 + (p->species == 2 ? 1 : 0);  // + phi
   L.species = p->species;
   L.ssize = p->storage == LB_STORE_F64 ? 8 : p->storage == LB_STORE_F32 ? 4 : 2;
   L.csize = p->compute == LB_COMPUTE_F64 ? 8 : 4;
@@ -120,8 +122,8 @@ Layout layout_of(const lb_params* p) {
 
 const Impl* select_impl(const lb_params* p) {
   switch (p->lattice) {
-    case LB_D2Q9: return impl_d2q9(p->storage);
-    case LB_D3Q19: return impl_d3q19(p->storage);
+    case LB_D2Q9: return impl_d2q9(p->storage, p->species);
+    case LB_D3Q19: return impl_d3q19(p->storage, p->species);
     case LB_D3Q27: return impl_d3q27(p->hermite_order, p->storage);
   }
   return nullptr;
@@ -228,6 +230,9 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
     h->partial = (double*)((char*)h->base + h->L.r_off);
     fill_params(h->p32, p, h->L, h->v2);
     fill_params(h->p64, p, h->L, h->v2);
+    const double pert = 2.25 * p->sigma / p->tau;  // (9/4) sigma omega
+    h->cp32 = {(float)pert, (float)p->beta};
+    h->cp64 = {pert, p->beta};
     hipError_t e = hipMemsetAsync(h->base, 0, h->L.total, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -253,8 +258,15 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
     if (!std::isfinite(rho[n])) return LB_ENONFINITE;
   for (int64_t n = 0; n < (int64_t)L.D * N; ++n)
     if (!std::isfinite(u[n])) return LB_ENONFINITE;
+  const bool two = h->p.species == 2;
+  if (two) {
+    for (int64_t n = 0; n < N; ++n) {
+      if (!std::isfinite(phi[n])) return LB_ENONFINITE;
+      if (phi[n] < -1.0 || phi[n] > 1.0) return LB_EINVAL;
+    }
+  }
   try {
-    const int per = 1 + L.D;  // doubles staged per node
+    const int per = 1 + L.D + (two ? 1 : 0);  // doubles staged per node
     const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
     const int64_t chunk = cap < N ? cap : N;
     std::vector<double> hb((size_t)per * chunk);
@@ -264,6 +276,7 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
       for (int64_t i = 0; i < cnt; ++i) hb[i] = rho[n0 + i] - h->p.rho0;
       for (int al = 0; al < L.D; ++al)
         std::memcpy(&hb[(size_t)(1 + al) * cnt], u + (size_t)al * N + n0, cnt * sizeof(double));
+      if (two) std::memcpy(&hb[(size_t)(1 + L.D) * cnt], phi + n0, cnt * sizeof(double));
       LB_TRY_HIP(hipMemcpyAsync(stage, hb.data(), (size_t)per * cnt * sizeof(double),
                                 hipMemcpyHostToDevice, h->stream));
       LB_TRY_HIP(h->impl->init(h, stage, n0, cnt));
@@ -305,13 +318,14 @@ int64_t lb_step_count(const lb_handle* h) { return h ? h->steps : -1; }
 int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
                double* conserved) {
   if (!h) return LB_EINVAL;
-  (void)phi;
   const Layout& L = h->L;
   const int64_t N = L.N;
+  const bool two = h->p.species == 2;
   const int K = L.D * (L.D + 1) / 2;
-  const int per = 1 + L.D + K;
+  const int per = 1 + L.D + K + (two ? 1 : 0);
+  if (!two) phi = nullptr;
   try {
-    if (rho || u || pineq) {
+    if (rho || u || pineq || phi) {
       const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
       const int64_t chunk = cap < N ? cap : N;
       std::vector<double> hb((size_t)per * chunk);
@@ -330,6 +344,8 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
           for (int q = 0; q < K; ++q)
             std::memcpy(pineq + (size_t)q * N + n0, &hb[(size_t)(1 + L.D + q) * cnt],
                         cnt * sizeof(double));
+        if (phi)
+          std::memcpy(phi + n0, &hb[(size_t)(1 + L.D + K) * cnt], cnt * sizeof(double));
       }
     }
     int st = LB_OK;
@@ -339,15 +355,15 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
       LB_TRY_HIP(hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, h->stream));
       LB_TRY_HIP(hipStreamSynchronize(h->stream));
-      double acc[4] = {0, 0, 0, 0};
+      double acc[5] = {0, 0, 0, 0, 0};
       for (int b = 0; b < kRedBlocks; ++b)
-        for (int q = 0; q < 4; ++q) acc[q] += part[(size_t)b * 8 + q];
+        for (int q = 0; q < 5; ++q) acc[q] += part[(size_t)b * 8 + q];
       conserved[0] = (double)N * h->p.rho0 + acc[0];
       conserved[1] = acc[1];
       conserved[2] = acc[2];
       conserved[3] = acc[3];
-      conserved[4] = conserved[0];
-      conserved[5] = 0.0;
+      conserved[4] = two ? acc[4] : conserved[0];
+      conserved[5] = two ? conserved[0] - acc[4] : 0.0;
       for (int q = 0; q < 4; ++q)
         if (!std::isfinite(conserved[q])) st = LB_ENONFINITE;
     } else {

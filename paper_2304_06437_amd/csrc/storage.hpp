@@ -11,10 +11,6 @@
 
 namespace lbk {
 
-struct bf16s {
-  uint16_t bits;
-};
-
 template <typename S, typename C>
 struct Codec;
 
@@ -37,60 +33,103 @@ struct Codec<_Float16, float> {
   __device__ static inline _Float16 store(float c) { return (_Float16)c; }
 };
 
+// fptrunc to bfloat: round to nearest, ties to even (v_cvt_pk_bf16_f32 on gfx950)
 template <>
-struct Codec<bf16s, float> {
-  __device__ static inline float load(bf16s s) {
-    return __uint_as_float(((uint32_t)s.bits) << 16);
-  }
-  // round to nearest, ties to even, on the upper 16 bits of the FP32 pattern
-  __device__ static inline bf16s store(float c) {
-    uint32_t u = __float_as_uint(c);
-    bf16s r;
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-      r.bits = (uint16_t)((u >> 16) | 0x0040u);  // quiet NaN
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);
-      r.bits = (uint16_t)(u >> 16);
-    }
-    return r;
-  }
+struct Codec<__bf16, float> {
+  __device__ static inline float load(__bf16 s) { return (float)s; }
+  __device__ static inline __bf16 store(float c) { return (__bf16)c; }
 };
 
-// V consecutive elements moved as one aligned block (global_load/store of
-// up to 16 bytes per instruction).
+// Streaming hints: population and moment arrays are touched once per sweep,
+// so loads and stores may bypass cache retention (nontemporal).
+#ifndef LB_NT_LOAD
+#define LB_NT_LOAD 1
+#endif
+#ifndef LB_NT_STORE
+#define LB_NT_STORE 1
+#endif
+
+// Raw aligned move of NB bytes (2, 4, 8, or a multiple of 16).
+template <int NB>
+struct RawT;
+template <>
+struct RawT<2> { using T = unsigned short; };
+template <>
+struct RawT<4> { using T = unsigned int; };
+template <>
+struct RawT<8> { typedef unsigned int T __attribute__((ext_vector_type(2))); };
+template <>
+struct RawT<16> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
+
+template <int NB, bool NT>
+__device__ __forceinline__ void raw_store(void* __restrict__ p, const void* src) {
+  if constexpr (NB > 16) {
+    static_assert(NB % 16 == 0, "raw_store size");
+#pragma unroll
+    for (int o = 0; o < NB; o += 16)
+      raw_store<16, NT>((char*)p + o, (const char*)src + o);
+  } else {
+    using T = typename RawT<NB>::T;
+    T v;
+    __builtin_memcpy(&v, src, NB);
+    if constexpr (NT) __builtin_nontemporal_store(v, (T*)p);
+    else *(T*)p = v;
+  }
+}
+
+template <int NB, bool NT>
+__device__ __forceinline__ void raw_load(const void* __restrict__ p, void* dst) {
+  if constexpr (NB > 16) {
+    static_assert(NB % 16 == 0, "raw_load size");
+#pragma unroll
+    for (int o = 0; o < NB; o += 16)
+      raw_load<16, NT>((const char*)p + o, (char*)dst + o);
+  } else {
+    using T = typename RawT<NB>::T;
+    T v;
+    if constexpr (NT) v = __builtin_nontemporal_load((const T*)p);
+    else v = *(const T*)p;
+    __builtin_memcpy(dst, &v, NB);
+  }
+}
+
 template <typename T, int V>
-struct alignas(V * sizeof(T) >= 16 ? 16 : V * sizeof(T)) Pack {
+struct Pack {
   T v[V];
 };
 
-template <typename S, typename C, int V>
-__device__ inline void load_pack(const S* __restrict__ p, C (&out)[V]) {
-  const Pack<S, V> pk = *reinterpret_cast<const Pack<S, V>*>(p);
+// V consecutive elements moved as one aligned block (the address must be
+// aligned to V * sizeof(T) bytes, up to 16).
+template <typename S, typename C, int V, bool NT = (LB_NT_LOAD != 0)>
+__device__ __forceinline__ void load_pack(const S* __restrict__ p, C (&out)[V]) {
+  Pack<S, V> pk;
+  raw_load<V * (int)sizeof(S), NT>(p, &pk);
 #pragma unroll
   for (int e = 0; e < V; ++e) out[e] = Codec<S, C>::load(pk.v[e]);
 }
 
-template <typename S, typename C, int V>
-__device__ inline void store_pack(S* __restrict__ p, const C (&in)[V]) {
+template <typename S, typename C, int V, bool NT = (LB_NT_STORE != 0)>
+__device__ __forceinline__ void store_pack(S* __restrict__ p, const C (&in)[V]) {
   Pack<S, V> pk;
 #pragma unroll
   for (int e = 0; e < V; ++e) pk.v[e] = Codec<S, C>::store(in[e]);
-  *reinterpret_cast<Pack<S, V>*>(p) = pk;
+  raw_store<V * (int)sizeof(S), NT>(p, &pk);
 }
 
-template <typename T, int V>
-__device__ inline void load_plain(const T* __restrict__ p, T (&out)[V]) {
-  const Pack<T, V> pk = *reinterpret_cast<const Pack<T, V>*>(p);
+template <typename T, int V, bool NT = (LB_NT_LOAD != 0)>
+__device__ __forceinline__ void load_plain(const T* __restrict__ p, T (&out)[V]) {
+  Pack<T, V> pk;
+  raw_load<V * (int)sizeof(T), NT>(p, &pk);
 #pragma unroll
   for (int e = 0; e < V; ++e) out[e] = pk.v[e];
 }
 
-template <typename T, int V>
-__device__ inline void store_plain(T* __restrict__ p, const T (&in)[V]) {
+template <typename T, int V, bool NT = (LB_NT_STORE != 0)>
+__device__ __forceinline__ void store_plain(T* __restrict__ p, const T (&in)[V]) {
   Pack<T, V> pk;
 #pragma unroll
   for (int e = 0; e < V; ++e) pk.v[e] = in[e];
-  *reinterpret_cast<Pack<T, V>*>(p) = pk;
+  raw_store<V * (int)sizeof(T), NT>(p, &pk);
 }
 
 }  // namespace lbk

@@ -77,12 +77,12 @@ class Simulation:
             pass
 
 
-def run(params: lb.lb_params, rho, u, nsteps: int, phi=None, **moment_kw):
+def run(params: lb.lb_params, rho, u, nsteps: int, phi=None, phi_out=False, **moment_kw):
     """Initialise, step and read back; returns the moments dict."""
     with Simulation(params) as sim:
         sim.init(rho, u, phi)
         sim.step(nsteps)
-        return sim.moments(**moment_kw)
+        return sim.moments(phi=phi_out, **moment_kw)
 
 
 def max_rel(a: np.ndarray, ref: np.ndarray) -> float:

@@ -63,6 +63,14 @@ def test_invalid_combinations_rejected():
     p = lb.lb_params_default()
     p.struct_size = 8
     assert lb.lb_validate(p) == lb.LB_EINVAL
+    two = dict(species=2, sigma=0.03, beta=0.7)
+    assert lb.lb_validate(lb.lb_params_default(**two)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(lattice=9, nz=1, **two)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(lattice=27, **two)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(storage=lb.LB_STORE_BF16S, **two)) == lb.LB_EUNSUPPORTED
+    assert lb.lb_validate(lb.lb_params_default(species=2, sigma=-1.0, beta=0.7)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(species=2, sigma=0.03, beta=1.5)) == lb.LB_EINVAL
+    assert lb.lb_validate(lb.lb_params_default(species=3)) == lb.LB_EINVAL
 
 
 def _golden_arrays():
