@@ -94,6 +94,27 @@ def cpu_baseline(seconds_hint: float = 15.0):
     }
 
 
+def serving(torch, jobs: int, rate: float, budget_gb: float):
+    """Continuous batching of a seeded Poisson request stream: D2Q9/D3Q19,
+    Taylor-Green or channel, FP32 or shifted-FP16 storage, edge
+    log-uniform 64..256 (n^2 or n^3), 200-2000 steps, admitted by an HBM
+    budget.  Time-to-solution = arrival to moments on the host."""
+    from paper_2304_06437_amd.serving import GpuBackend, Server, poisson_mix
+
+    specs = poisson_mix(jobs, rate=rate, seed=2026)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        be = GpuBackend()
+        rep = Server(be, hbm_budget=int(budget_gb * 1e9), chunk_steps=200).run(specs)
+        be.close()
+    torch.cuda.synchronize()
+    s = rep.summary()
+    s.update({"rate_per_s": rate, "budget_GB": budget_gb,
+              "mix": "D2Q9/D3Q19 x TG/channel x f32/f16s, edge 64..256 log-uniform, "
+                     "200-2000 steps, seeded Poisson arrivals"})
+    return s
+
+
 def copy_ceiling(torch, nbytes: int = 4 << 30, reps: int = 10):
     """Device-to-device copy kernel bandwidth (read + write bytes / time)."""
     from paper_2304_06437_amd import lb
@@ -126,6 +147,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=96,
+                    help="requests in the serving measurement (0 to skip)")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -214,6 +239,8 @@ def main():
         "copy_ceiling_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "mass_finite": bool(np.isfinite(check[0])),
     }
+    if args.serve_jobs > 0:
+        out["serving"] = serving(torch, args.serve_jobs, args.serve_rate, args.serve_budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

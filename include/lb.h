@@ -159,6 +159,35 @@ int lb_destroy(lb_handle* h);
 /* Static description of a status code.  Never NULL. */
 const char* lb_strerror(int status);
 
+/* ---- batched execution (serving many independent simulations) -------- */
+
+typedef struct lb_batch lb_batch;
+
+/* Create a batch executor enqueueing on hip_stream (borrowed; every handle
+ * passed to lb_batch_step must have been created on the same stream).
+ * Not part of the paper: it packs independent simulations so that small
+ * domains share launches. */
+int lb_batch_create(void* hip_stream, lb_batch** out);
+
+/* Advance handles[i] by nsteps[i] >= 0 steps (distinct handles, count >= 0).
+ * Handles with the same kernel configuration (lattice, Hermite order,
+ * species, storage, compute, row vector width) share one moments launch and
+ * one stream-collide launch per step; a handle whose step count is reached
+ * drops out of later launches.  Each handle's result is bitwise the same as
+ * when it is stepped in a batch of its own.  Runs of >= 3 steps with a fixed
+ * set of handles are captured once as a HIP graph and replayed (unless
+ * disabled with lb_batch_set_graphs); the call returns after the graph
+ * replays complete.  The descriptor tables live in device and pinned host
+ * buffers owned by the batch, grown on demand.  LB_EINVAL for NULL or
+ * duplicate handles, negative counts, or a handle on another stream. */
+int lb_batch_step(lb_batch* b, lb_handle* const* handles, const int64_t* nsteps, int count);
+
+/* Enable (default) or disable graph capture of batched step runs. */
+int lb_batch_set_graphs(lb_batch* b, int enable);
+
+/* Destroy a batch executor (waits for its stream).  NULL is accepted. */
+int lb_batch_destroy(lb_batch* b);
+
 /* ---- instrumentation ------------------------------------------------- */
 
 /* Start per-kernel timing: the next lb_step calls record HIP events around

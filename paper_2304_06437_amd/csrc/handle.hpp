@@ -8,6 +8,9 @@
 
 #include "kernels.hpp"
 #include "kernels2.hpp"
+#include "kernels_batch.hpp"
+
+#include <cstring>
 #include "lb.h"
 
 namespace lbk {
@@ -56,7 +59,17 @@ struct Impl {
   hipError_t (*init)(const lb_handle*, const double*, int64_t, int64_t);
   hipError_t (*readout)(const lb_handle*, double*, int64_t, int64_t);
   hipError_t (*conserved)(const lb_handle*);
+  // batched execution (lb_batch_step)
+  size_t desc_size;
+  void (*fill_desc)(const lb_handle*, void* dst, int64_t start);
+  int64_t (*units_moments)(const lb_handle*);
+  int64_t (*units_sc)(const lb_handle*);
+  hipError_t (*batch_moments)(const void* d_desc, int n, int64_t total, hipStream_t s);
+  hipError_t (*batch_sc)(const void* d_desc, int n, int64_t total, int v2, hipStream_t s);
 };
+
+template <typename C>
+inline void fill_job_desc(const lb_handle* h, void* dst, int64_t start);
 
 template <typename C>
 inline const StepParams<C>& params_of(const lb_handle* h);
@@ -70,6 +83,18 @@ template <>
 inline const ColourParams<float>& colour_of<float>(const lb_handle* h) { return h->cp32; }
 template <>
 inline const ColourParams<double>& colour_of<double>(const lb_handle* h) { return h->cp64; }
+
+template <typename C>
+inline void fill_job_desc(const lb_handle* h, void* dst, int64_t start) {
+  JobDesc<C> d;
+  std::memset(&d, 0, sizeof(d));
+  d.p = params_of<C>(h);
+  d.cp = colour_of<C>(h);
+  d.m = h->m;
+  d.f = h->f;
+  d.start = start;
+  std::memcpy(dst, &d, sizeof(d));
+}
 
 template <class L, int ORDER, typename S, typename C, int V1, int V2MAX>
 struct ImplT {
@@ -127,8 +152,46 @@ struct ImplT {
                        (const S*)h->f, h->partial, h->L.N, p);
     return hipGetLastError();
   }
+  static int64_t units_moments(const lb_handle* h) { return params_of<C>(h).npad / V1 / 256; }
+  static int64_t units_sc(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    return p.nseg * p.ny * p.nz;
+  }
+  static hipError_t batch_moments(const void* d, int n, int64_t total, hipStream_t s) {
+    hipLaunchKernelGGL((k_moments_batch<L, 1, S, C, V1>), dim3((unsigned)total), dim3(256), 0, s,
+                       (const JobDesc<C>*)d, n);
+    return hipGetLastError();
+  }
+  template <int V>
+  static hipError_t bsc(const void* d, int n, int64_t total, hipStream_t s) {
+    constexpr int EMAX = 16 / (int)(sizeof(S) > sizeof(C) ? sizeof(S) : sizeof(C));
+    constexpr int E = V < EMAX ? V : EMAX;
+    constexpr int HH = V / E;
+    hipLaunchKernelGGL((k_stream_collide_batch<L, ORDER, 1, S, C, E, HH>),
+                       dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const JobDesc<C>*)d,
+                       n, total);
+    return hipGetLastError();
+  }
+  static hipError_t batch_sc(const void* d, int n, int64_t total, int v2, hipStream_t s) {
+    switch (v2) {
+      case 8:
+        if constexpr (V2MAX >= 8) return bsc<8>(d, n, total, s);
+        break;
+      case 4:
+        if constexpr (V2MAX >= 4) return bsc<4>(d, n, total, s);
+        break;
+      case 2:
+        return bsc<2>(d, n, total, s);
+      case 1:
+        return bsc<1>(d, n, total, s);
+    }
+    return hipErrorInvalidValue;
+  }
   static const Impl* get() {
-    static const Impl impl = {V1, V2MAX, &moments, &stream_collide, &init, &readout, &conserved};
+    static const Impl impl = {V1,           V2MAX,          &moments,       &stream_collide,
+                              &init,        &readout,       &conserved,     sizeof(JobDesc<C>),
+                              &fill_job_desc<C>, &units_moments, &units_sc, &batch_moments,
+                              &batch_sc};
     return &impl;
   }
 };
@@ -194,8 +257,40 @@ struct ImplT2 {
                        (const S*)h->f, h->partial, h->L.N, p);
     return hipGetLastError();
   }
+  static int64_t units_moments(const lb_handle* h) { return params_of<C>(h).npad / V1 / 256; }
+  static int64_t units_sc(const lb_handle* h) {
+    const auto& p = params_of<C>(h);
+    return p.nseg * p.ny * p.nz;
+  }
+  static hipError_t batch_moments(const void* d, int n, int64_t total, hipStream_t s) {
+    hipLaunchKernelGGL((k_moments_batch<L, 2, S, C, V1>), dim3((unsigned)total), dim3(256), 0, s,
+                       (const JobDesc<C>*)d, n);
+    return hipGetLastError();
+  }
+  template <int E>
+  static hipError_t bsc(const void* d, int n, int64_t total, hipStream_t s) {
+    hipLaunchKernelGGL((k_stream_collide_batch<L, 2, 2, S, C, E, 1>),
+                       dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const JobDesc<C>*)d,
+                       n, total);
+    return hipGetLastError();
+  }
+  static hipError_t batch_sc(const void* d, int n, int64_t total, int v2, hipStream_t s) {
+    switch (v2) {
+      case 4:
+        if constexpr (V2MAX >= 4) return bsc<4>(d, n, total, s);
+        break;
+      case 2:
+        return bsc<2>(d, n, total, s);
+      case 1:
+        return bsc<1>(d, n, total, s);
+    }
+    return hipErrorInvalidValue;
+  }
   static const Impl* get() {
-    static const Impl impl = {V1, V2MAX, &moments, &stream_collide, &init, &readout, &conserved};
+    static const Impl impl = {V1,           V2MAX,          &moments,       &stream_collide,
+                              &init,        &readout,       &conserved,     sizeof(JobDesc<C>),
+                              &fill_job_desc<C>, &units_moments, &units_sc, &batch_moments,
+                              &batch_sc};
     return &impl;
   }
 };

@@ -248,10 +248,9 @@ __device__ __forceinline__ double lane_bcast(double v, int src) { return __shfl(
 // (padded) arrays; all loads and stores are V-wide vectors.
 // -------------------------------------------------------------------------
 template <class L, typename S, typename C, int V>
-__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __restrict__ m,
-                                                 StepParams<C> p) {
+__device__ __forceinline__ void moments_body(const S* __restrict__ f, C* __restrict__ m,
+                                             const StepParams<C>& p, int64_t i0) {
   using ML = MomentLayout<L>;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
   if (i0 >= p.npad) return;
   C s[L::Q][V];
 #pragma unroll
@@ -270,6 +269,12 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
   }
 #pragma unroll
   for (int q = 0; q < ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+}
+
+template <class L, typename S, typename C, int V>
+__global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __restrict__ m,
+                                                 StepParams<C> p) {
+  moments_body<L, S, C, V>(f, m, p, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V);
 }
 
 // -------------------------------------------------------------------------
@@ -387,9 +392,10 @@ struct StreamCollide {
     post_collision<L, ORDER, C>(mm, p, k);
   }
 
-  __device__ static void run(const C* __restrict__ m, S* __restrict__ f, const StepParams<C>& p) {
+  // One wavefront: row segment number `wave` of the domain (wave-uniform).
+  __device__ static void run_wave(const C* __restrict__ m, S* __restrict__ f,
+                                  const StepParams<C>& p, int64_t wave) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t rows = p.ny * p.nz;
     if (wave >= p.nseg * rows) return;  // whole wavefront leaves together
     const int64_t seg = wave % p.nseg;
@@ -484,7 +490,8 @@ struct StreamCollide {
 template <class L, int ORDER, typename S, typename C, int E, int H>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  StreamCollide<L, ORDER, S, C, E, H>::run(m, f, p);
+  StreamCollide<L, ORDER, S, C, E, H>::run_wave(
+      m, f, p, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // -------------------------------------------------------------------------

@@ -60,10 +60,9 @@ struct ColourLayout {
 // Moments sweep: mixture moments from set 0, red density from set 1, and
 // phi = (2 rho_R - rho)/rho.
 template <class L, typename S, typename C, int V>
-__global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __restrict__ m,
-                                                  StepParams<C> p) {
+__device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __restrict__ m,
+                                              const StepParams<C>& p, int64_t i0) {
   using ML = MomentLayout<L>;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
   if (i0 >= p.npad) return;
   C s[L::Q][V];
   C rr[V];
@@ -92,6 +91,12 @@ __global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __
   }
 #pragma unroll
   for (int q = 0; q <= ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+}
+
+template <class L, typename S, typename C, int V>
+__global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __restrict__ m,
+                                                  StepParams<C> p) {
+  moments2_body<L, S, C, V>(f, m, p, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V);
 }
 
 // Phase field of node (x + dx, ty, tz) given the wrapped/validated row
@@ -311,11 +316,11 @@ struct StreamCollide2 {
     }
   }
 
-  __device__ static void run(const C* __restrict__ m, S* __restrict__ f, const StepParams<C>& p,
-                             const ColourParams<C>& cp) {
+  __device__ static void run_wave(const C* __restrict__ m, S* __restrict__ f,
+                                  const StepParams<C>& p, const ColourParams<C>& cp,
+                                  int64_t wave) {
     constexpr int D = L::D;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t rows = p.ny * p.nz;
     if (wave >= p.nseg * rows) return;
     const int64_t seg = wave % p.nseg;
@@ -486,7 +491,8 @@ template <class L, typename S, typename C, int E>
 __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m,
                                                          S* __restrict__ f, StepParams<C> p,
                                                          ColourParams<C> cp) {
-  StreamCollide2<L, S, C, E>::run(m, f, p, cp);
+  StreamCollide2<L, S, C, E>::run_wave(m, f, p, cp,
+                                       (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.

@@ -12,10 +12,13 @@
 // beyond lb_required_bytes on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "handle.hpp"
@@ -447,6 +450,210 @@ int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
                      (const uint4*)src, (uint4*)dst, n16);
   return launch_status(hipGetLastError());
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched execution
+// ---------------------------------------------------------------------------
+struct lb_batch {
+  hipStream_t stream = nullptr;
+  void* d_buf = nullptr;
+  size_t d_cap = 0;
+  void* h_buf = nullptr;  // pinned staging for the descriptor tables
+  size_t h_cap = 0;
+  hipEvent_t copied = nullptr;
+  bool copy_pending = false;
+  int graphs = 1;
+};
+
+namespace {
+
+struct BatchGroup {
+  const Impl* impl;
+  int v2;
+  std::vector<int> jobs;    // indices into the handle array, input order
+  size_t off_k1 = 0, off_k2 = 0;  // byte offsets of the two tables
+  int64_t units_k1 = 0, units_k2 = 0;
+};
+
+struct BatchSegment {
+  int64_t steps = 0;
+  std::vector<BatchGroup> groups;
+};
+
+hipError_t launch_segment_step(const lb_batch* b, const BatchSegment& seg) {
+  for (const auto& g : seg.groups) {
+    hipError_t e = g.impl->batch_moments((const char*)b->d_buf + g.off_k1, (int)g.jobs.size(),
+                                         g.units_k1, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (const auto& g : seg.groups) {
+    hipError_t e = g.impl->batch_sc((const char*)b->d_buf + g.off_k2, (int)g.jobs.size(),
+                                    g.units_k2, g.v2, b->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_batch_create(void* hip_stream, lb_batch** out) {
+  if (!out) return LB_EINVAL;
+  *out = nullptr;
+  try {
+    lb_batch* b = new lb_batch();
+    b->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete b;
+      return status_of(e);
+    }
+    *out = b;
+    return LB_OK;
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  }
+}
+
+int lb_batch_set_graphs(lb_batch* b, int enable) {
+  if (!b) return LB_EINVAL;
+  b->graphs = enable ? 1 : 0;
+  return LB_OK;
+}
+
+int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int count) {
+  if (!b || count < 0 || (count > 0 && (!hs || !nsteps))) return LB_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i] || nsteps[i] < 0) return LB_EINVAL;
+    if (hs[i]->stream != b->stream) return LB_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return LB_EINVAL;
+  }
+  if (count == 0) return LB_OK;
+  try {
+    // segments of constant active set: jobs sorted by their step counts
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return nsteps[a] < nsteps[c]; });
+    std::vector<BatchSegment> segs;
+    int64_t done = 0;
+    for (int k = 0; k < count; ++k) {
+      const int64_t target = nsteps[order[k]];
+      if (target <= done) continue;
+      BatchSegment seg;
+      seg.steps = target - done;
+      // active: every job with nsteps > done, grouped by kernel configuration
+      std::map<std::pair<const Impl*, int>, size_t> gidx;
+      for (int i = 0; i < count; ++i) {
+        if (nsteps[i] <= done) continue;
+        const auto key = std::make_pair(hs[i]->impl, hs[i]->v2);
+        auto it = gidx.find(key);
+        if (it == gidx.end()) {
+          gidx[key] = seg.groups.size();
+          BatchGroup g;
+          g.impl = hs[i]->impl;
+          g.v2 = hs[i]->v2;
+          seg.groups.push_back(g);
+          it = gidx.find(key);
+        }
+        seg.groups[it->second].jobs.push_back(i);
+      }
+      segs.push_back(std::move(seg));
+      done = target;
+    }
+    // descriptor tables of every segment in one staging block
+    size_t bytes = 0;
+    for (auto& seg : segs)
+      for (auto& g : seg.groups) {
+        const size_t tb = align_up(g.impl->desc_size * g.jobs.size(), 256);
+        g.off_k1 = bytes;
+        bytes += tb;
+        g.off_k2 = bytes;
+        bytes += tb;
+      }
+    if (b->copy_pending) {
+      LB_TRY_HIP(hipEventSynchronize(b->copied));
+      b->copy_pending = false;
+    }
+    if (bytes > b->h_cap) {
+      if (b->h_buf) (void)hipHostFree(b->h_buf);
+      b->h_buf = nullptr;
+      b->h_cap = 0;
+      LB_TRY_HIP(hipHostMalloc(&b->h_buf, bytes, hipHostMallocDefault));
+      b->h_cap = bytes;
+    }
+    if (bytes > b->d_cap) {
+      LB_TRY_HIP(hipStreamSynchronize(b->stream));  // old tables may still be in use
+      if (b->d_buf) (void)hipFree(b->d_buf);
+      b->d_buf = nullptr;
+      b->d_cap = 0;
+      LB_TRY_HIP(hipMalloc(&b->d_buf, bytes));
+      b->d_cap = bytes;
+    }
+    for (auto& seg : segs)
+      for (auto& g : seg.groups) {
+        int64_t u1 = 0, u2 = 0;
+        for (size_t q = 0; q < g.jobs.size(); ++q) {
+          const lb_handle* h = hs[g.jobs[q]];
+          g.impl->fill_desc(h, (char*)b->h_buf + g.off_k1 + q * g.impl->desc_size, u1);
+          g.impl->fill_desc(h, (char*)b->h_buf + g.off_k2 + q * g.impl->desc_size, u2);
+          u1 += g.impl->units_moments(h);
+          u2 += g.impl->units_sc(h);
+        }
+        g.units_k1 = u1;
+        g.units_k2 = u2;
+      }
+    LB_TRY_HIP(hipMemcpyAsync(b->d_buf, b->h_buf, bytes, hipMemcpyHostToDevice, b->stream));
+    LB_TRY_HIP(hipEventRecord(b->copied, b->stream));
+    b->copy_pending = true;
+    for (const auto& seg : segs) {
+      const bool graph = b->graphs && b->stream != nullptr && seg.steps >= 3;
+      if (graph) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        LB_TRY_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+        hipError_t le = launch_segment_step(b, seg);
+        hipError_t ce = hipStreamEndCapture(b->stream, &gr);
+        if (le != hipSuccess) return status_of(le);
+        if (ce != hipSuccess) return status_of(ce);
+        hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+          (void)hipGraphDestroy(gr);
+          return status_of(ie);
+        }
+        hipError_t ge = hipSuccess;
+        for (int64_t s = 0; s < seg.steps && ge == hipSuccess; ++s) ge = hipGraphLaunch(ex, b->stream);
+        hipError_t se = hipStreamSynchronize(b->stream);
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(gr);
+        if (ge != hipSuccess) return status_of(ge);
+        if (se != hipSuccess) return status_of(se);
+      } else {
+        for (int64_t s = 0; s < seg.steps; ++s) LB_TRY_HIP(launch_segment_step(b, seg));
+      }
+    }
+    for (int i = 0; i < count; ++i) hs[i]->steps += nsteps[i];
+    return LB_OK;
+  } catch (const std::bad_alloc&) {
+    return LB_ENOMEM;
+  }
+}
+
+int lb_batch_destroy(lb_batch* b) {
+  if (!b) return LB_OK;
+  int st = LB_OK;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) st = status_of(e);
+  if (b->d_buf) (void)hipFree(b->d_buf);
+  if (b->h_buf) (void)hipHostFree(b->h_buf);
+  if (b->copied) (void)hipEventDestroy(b->copied);
+  delete b;
+  return st;
 }
 
 }  // extern "C"

@@ -87,6 +87,11 @@ def load():
     lib.lb_timing_begin.argtypes = [H, ctypes.c_int64]
     lib.lb_timing_end.argtypes = [H, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.lb_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.lb_batch_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.lb_batch_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.lb_batch_destroy.argtypes = [ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -211,3 +216,25 @@ def lb_timing_end(h):
 def lb_copy(dst: int, src: int, nbytes: int, hip_stream: int = 0):
     _check(load().lb_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes,
                           ctypes.c_void_p(hip_stream or None)), "lb_copy")
+
+
+def lb_batch_create(hip_stream: int = 0):
+    b = ctypes.c_void_p()
+    _check(load().lb_batch_create(ctypes.c_void_p(hip_stream or None), ctypes.byref(b)),
+           "lb_batch_create")
+    return b
+
+
+def lb_batch_step(b, handles, nsteps):
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.value for h in handles])
+    ns = (ctypes.c_int64 * n)(*[int(k) for k in nsteps])
+    _check(load().lb_batch_step(b, hs, ns, n), "lb_batch_step")
+
+
+def lb_batch_set_graphs(b, enable: bool):
+    _check(load().lb_batch_set_graphs(b, 1 if enable else 0), "lb_batch_set_graphs")
+
+
+def lb_batch_destroy(b):
+    _check(load().lb_batch_destroy(b), "lb_batch_destroy")

@@ -1,0 +1,315 @@
+"""Continuous batching of independent lattice Boltzmann simulations.
+
+A request is one simulation (lattice, domain, relaxation time, initial flow,
+storage precision, number of steps).  The server
+
+  * admits queued requests in arrival order while their device footprint
+    (``lb_required_bytes``) fits the HBM budget, whenever memory frees up;
+  * keeps every admitted simulation resident on the GPU and advances all of
+    them together, ``chunk_steps`` at a time, through ``lb_batch_step``
+    (simulations of the same kernel configuration share one launch per
+    sweep; fixed-membership runs are replayed from a captured HIP graph);
+  * reads each finished simulation's moments back, records its
+    time-to-solution (arrival to moments on the host) and releases its memory.
+
+Requests that arrive while others are running join at the next chunk
+boundary.  A request whose footprint exceeds the whole budget is rejected; a
+request whose set-up or read-out fails (or whose state became non-finite) is
+marked failed without affecting the others.
+
+Not part of the paper: the serving loop is how this library runs many small
+independent simulations on one GPU.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclass
+class JobSpec:
+    job_id: int
+    lattice: int                  # 9, 19 or 27
+    shape: tuple                  # (nx, ny, nz); nz = 1 for D2Q9
+    steps: int
+    storage: str = "f32"          # f32, f16s, bf16s, f64
+    flow: str = "tg"              # "tg" (Taylor-Green) or "channel"
+    tau: float = 0.6
+    arrival: float = 0.0          # seconds after the start of the run
+
+    @property
+    def nodes(self) -> int:
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    def fields(self):
+        """Initial density and velocity of the request's flow."""
+        nx, ny, nz = self.shape
+        D = 2 if self.lattice == 9 else 3
+        if self.flow == "tg":
+            if D == 2:
+                return inputs.taylor_green_2d(nx, ny, 0.01)
+            return inputs.taylor_green_3d(nx, ny, nz, 0.01)
+        if self.flow == "channel":
+            return inputs.channel_noise(nx, ny, nz, D, seed=12345 + self.job_id)
+        raise ValueError(self.flow)
+
+    def force(self):
+        return (1e-6, 0.0, 0.0) if self.flow == "channel" else (0.0, 0.0, 0.0)
+
+    def bc(self):
+        if self.flow != "channel":
+            return (0, 0, 0)
+        return (0, 1, 0) if self.lattice == 9 else (0, 0, 1)
+
+
+@dataclass
+class JobResult:
+    job_id: int
+    status: str                   # done, failed, rejected
+    arrival: float
+    admitted: float = math.nan
+    finished: float = math.nan
+    lattice_updates: int = 0
+    error: str = ""
+    moments: dict | None = None
+
+    @property
+    def time_to_solution(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclass
+class ServeReport:
+    results: list
+    makespan: float
+    max_active: int
+    peak_bytes: int
+    chunks: int = 0
+
+    def _tts(self):
+        return np.array([r.time_to_solution for r in self.results if r.status == "done"])
+
+    @property
+    def p50(self) -> float:
+        t = self._tts()
+        return float(np.percentile(t, 50)) if t.size else math.nan
+
+    @property
+    def p99(self) -> float:
+        t = self._tts()
+        return float(np.percentile(t, 99)) if t.size else math.nan
+
+    @property
+    def lattice_updates(self) -> int:
+        return sum(r.lattice_updates for r in self.results if r.status == "done")
+
+    @property
+    def mlups(self) -> float:
+        return self.lattice_updates / self.makespan / 1e6 if self.makespan > 0 else math.nan
+
+    def summary(self) -> dict:
+        st = [r.status for r in self.results]
+        return {
+            "jobs": len(st), "done": st.count("done"), "failed": st.count("failed"),
+            "rejected": st.count("rejected"), "p50_s": round(self.p50, 4),
+            "p99_s": round(self.p99, 4), "aggregate_MLUPS": round(self.mlups, 1),
+            "makespan_s": round(self.makespan, 3), "max_active": self.max_active,
+            "peak_GB": round(self.peak_bytes / 1e9, 3), "chunks": self.chunks,
+        }
+
+
+class _Active:
+    __slots__ = ("spec", "handle", "remaining", "nbytes", "result")
+
+    def __init__(self, spec, handle, nbytes, result):
+        self.spec = spec
+        self.handle = handle
+        self.remaining = spec.steps
+        self.nbytes = nbytes
+        self.result = result
+
+
+class GpuBackend:
+    """liblb.so simulations in torch-owned device memory on one stream."""
+
+    def __init__(self, device=None, graphs: bool = True, keep_moments: bool = False):
+        import torch
+
+        from . import lb
+
+        self.torch = torch
+        self.lb = lb
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.batch = lb.lb_batch_create(self.stream.cuda_stream)
+        lb.lb_batch_set_graphs(self.batch, graphs)
+        self.keep_moments = keep_moments
+
+    def params(self, spec: JobSpec):
+        from .sim import make_params
+
+        return make_params(lattice=spec.lattice, shape=spec.shape, tau=spec.tau,
+                           force=spec.force(), bc=spec.bc(), storage=spec.storage)
+
+    def required_bytes(self, spec: JobSpec) -> int:
+        n = self.lb.lb_required_bytes(self.params(spec))
+        if n == 0:
+            raise ValueError(f"invalid request {spec}")
+        return n
+
+    def create(self, spec: JobSpec):
+        from .sim import Simulation
+
+        sim = Simulation(self.params(spec), device=self.device, stream=self.stream)
+        rho, u = spec.fields()
+        sim.init(rho, u)
+        return sim
+
+    def step(self, handles, nsteps):
+        self.lb.lb_batch_step(self.batch, [s.handle for s in handles], nsteps)
+
+    def read(self, sim, spec: JobSpec) -> dict:
+        out = sim.moments(rho=self.keep_moments, u=True, pineq=False, allow_nonfinite=True)
+        if out["status"] != self.lb.LB_OK or not np.isfinite(out["u"]).all():
+            raise FloatingPointError("non-finite state")
+        return out
+
+    def destroy(self, sim):
+        sim.close()
+
+    def close(self):
+        if self.batch is not None:
+            self.lb.lb_batch_destroy(self.batch)
+            self.batch = None
+
+
+class Server:
+    def __init__(self, backend, hbm_budget: int, chunk_steps: int = 200,
+                 max_active: int = 256, keep_moments: bool = False, clock=time.perf_counter,
+                 sleep=time.sleep):
+        self.backend = backend
+        self.budget = int(hbm_budget)
+        self.chunk = int(chunk_steps)
+        self.max_active = int(max_active)
+        self.keep_moments = keep_moments
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, specs) -> ServeReport:
+        pending = deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
+        queue: deque = deque()
+        active: list = []
+        results = {}
+        used = peak = 0
+        max_active = chunks = 0
+        t0 = self.clock()
+
+        def now():
+            return self.clock() - t0
+
+        while pending or queue or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.popleft())
+            # admission: arrival order, as long as the head of the queue fits
+            while queue and len(active) < self.max_active:
+                spec = queue[0]
+                res = JobResult(spec.job_id, "queued", spec.arrival)
+                try:
+                    need = self.backend.required_bytes(spec)
+                except Exception as e:  # invalid request
+                    queue.popleft()
+                    res.status, res.error = "rejected", str(e)
+                    results[spec.job_id] = res
+                    continue
+                if need > self.budget:
+                    queue.popleft()
+                    res.status, res.error = "rejected", f"needs {need} B > budget {self.budget} B"
+                    results[spec.job_id] = res
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.popleft()
+                res.admitted = now()
+                try:
+                    handle = self.backend.create(spec)
+                except Exception as e:
+                    res.status, res.error, res.finished = "failed", repr(e), now()
+                    results[spec.job_id] = res
+                    continue
+                used += need
+                peak = max(peak, used)
+                active.append(_Active(spec, handle, need, res))
+            max_active = max(max_active, len(active))
+            if not active:
+                if pending and not queue:
+                    self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                continue
+            # one chunk for every resident simulation
+            nsteps = [min(self.chunk, a.remaining) for a in active]
+            try:
+                self.backend.step([a.handle for a in active], nsteps)
+            except Exception as e:
+                # a launch failure poisons the whole batch: fail every member
+                for a in active:
+                    a.result.status, a.result.error, a.result.finished = "failed", repr(e), now()
+                    results[a.spec.job_id] = a.result
+                    self._release(a)
+                    used -= a.nbytes
+                active = []
+                continue
+            chunks += 1
+            still = []
+            for a, k in zip(active, nsteps):
+                a.remaining -= k
+                if a.remaining > 0:
+                    still.append(a)
+                    continue
+                try:
+                    out = self.backend.read(a.handle, a.spec)
+                    a.result.status = "done"
+                    a.result.lattice_updates = a.spec.nodes * a.spec.steps
+                    if self.keep_moments:
+                        a.result.moments = out
+                except Exception as e:
+                    a.result.status, a.result.error = "failed", repr(e)
+                a.result.finished = now()
+                results[a.spec.job_id] = a.result
+                self._release(a)
+                used -= a.nbytes
+            active = still
+        ordered = [results[s.job_id] for s in sorted(specs, key=lambda s: s.job_id)]
+        return ServeReport(ordered, now(), max_active, peak, chunks)
+
+    def _release(self, a):
+        try:
+            self.backend.destroy(a.handle)
+        except Exception:
+            pass
+
+
+def poisson_mix(n_jobs: int, rate: float, seed: int = 2026, edge_min: int = 64,
+                edge_max: int = 256, steps=(200, 2000), lattices=(9, 19),
+                storages=("f32", "f16s"), flows=("tg", "channel")) -> list:
+    """Seeded request stream: exponential inter-arrival gaps (mean 1/rate),
+    lattice / flow / storage uniform, edge n = round(exp U[ln min, ln max])
+    (n^2 for D2Q9, n^3 otherwise), step count uniform in [steps]."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    specs = []
+    for i in range(n_jobs):
+        t += rng.exponential(1.0 / rate)
+        lat = int(rng.choice(lattices))
+        n = int(round(math.exp(rng.uniform(math.log(edge_min), math.log(edge_max)))))
+        shape = (n, n, 1) if lat == 9 else (n, n, n)
+        specs.append(JobSpec(job_id=i, lattice=lat, shape=shape,
+                             steps=int(rng.integers(steps[0], steps[1] + 1)),
+                             storage=str(rng.choice(storages)), flow=str(rng.choice(flows)),
+                             tau=0.6, arrival=t))
+    return specs

@@ -1,0 +1,129 @@
+"""Batched execution and the serving loop on the GPU."""
+import numpy as np
+import pytest
+
+from paper_2304_06437_amd import inputs, lb
+from paper_2304_06437_amd.serving import GpuBackend, JobSpec, Server, poisson_mix
+from paper_2304_06437_amd.sim import Simulation, make_params, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(spec):
+    p = make_params(lattice=spec.lattice, shape=spec.shape, tau=spec.tau, force=spec.force(),
+                    bc=spec.bc(), storage=spec.storage)
+    s = Simulation(p)
+    rho, u = spec.fields()
+    s.init(rho, u)
+    return s
+
+
+MIX = [
+    JobSpec(0, 19, (40, 24, 20), 300, storage="f32", flow="tg"),
+    JobSpec(1, 9, (96, 64, 1), 500, storage="f32", flow="channel"),
+    JobSpec(2, 19, (64, 16, 12), 120, storage="f16s", flow="channel"),
+    JobSpec(3, 19, (33, 17, 9), 300, storage="f32", flow="channel"),
+    JobSpec(4, 27, (24, 12, 10), 77, storage="f32", flow="tg"),
+    JobSpec(5, 9, (128, 32, 1), 300, storage="bf16s", flow="tg"),
+    JobSpec(6, 19, (128, 8, 8), 1, storage="f32", flow="tg"),
+]
+
+
+_STREAM = None
+
+
+def _stream():
+    """A non-default stream, so that batched runs can be graph-captured."""
+    import torch
+
+    global _STREAM
+    if _STREAM is None:
+        _STREAM = torch.cuda.Stream()
+    return _STREAM
+
+
+def _batch_run(specs, graphs=True):
+    import torch
+
+    with torch.cuda.stream(_stream()):
+        sims = [_sim(s) for s in specs]
+        b = lb.lb_batch_create(torch.cuda.current_stream().cuda_stream)
+        lb.lb_batch_set_graphs(b, graphs)
+        lb.lb_batch_step(b, [s.handle for s in sims], [s.steps for s in specs])
+        out = [sim.moments(phi=False) for sim in sims]
+        counts = [lb.lb_step_count(sim.handle) for sim in sims]
+        lb.lb_batch_destroy(b)
+        for sim in sims:
+            sim.close()
+    assert counts == [s.steps for s in specs]
+    return out
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
+    mixed = _batch_run(MIX)
+    for spec, got in zip(MIX, mixed):
+        alone = _batch_run([spec])[0]
+        for k in ("rho", "u", "pineq"):
+            assert np.array_equal(got[k], alone[k]), (spec.job_id, k)
+
+
+def test_graph_replay_matches_direct_launches():
+    a = _batch_run(MIX, graphs=True)
+    b = _batch_run(MIX, graphs=False)
+    for x, y in zip(a, b):
+        for k in ("rho", "u", "pineq"):
+            assert np.array_equal(x[k], y[k])
+
+
+def test_batched_equals_single_job_path():
+    for spec in MIX[:5]:
+        sim = _sim(spec)
+        sim.step(spec.steps)
+        single = sim.moments()
+        sim.close()
+        batched = _batch_run([spec])[0]
+        err = max_rel(batched["u"], single["u"])
+        print(f"job {spec.job_id}: batched vs single max-rel u {err:.2e}")
+        assert err <= 1e-6
+
+
+def test_batch_rejects_bad_arguments():
+    import torch
+
+    spec = MIX[0]
+    sim = _sim(spec)
+    b = lb.lb_batch_create(torch.cuda.current_stream().cuda_stream)
+    with pytest.raises(lb.LbError):
+        lb.lb_batch_step(b, [sim.handle, sim.handle], [1, 1])  # duplicate
+    with pytest.raises(lb.LbError):
+        lb.lb_batch_step(b, [sim.handle], [-1])
+    side = torch.cuda.Stream()
+    b2 = lb.lb_batch_create(side.cuda_stream)
+    with pytest.raises(lb.LbError):
+        lb.lb_batch_step(b2, [sim.handle], [1])  # handle on another stream
+    lb.lb_batch_step(b, [sim.handle], [0])
+    lb.lb_batch_destroy(b)
+    lb.lb_batch_destroy(b2)
+    sim.close()
+
+
+def test_serving_loop_end_to_end():
+    """Small Poisson stream with a budget that forces queueing: every request
+    completes, and a sample of results equals the request run on its own."""
+    import torch
+
+    specs = poisson_mix(24, rate=200.0, seed=11, edge_min=24, edge_max=64, steps=(50, 300))
+    with torch.cuda.stream(_stream()):
+        be = GpuBackend(keep_moments=True)
+        budget = 3 * max(be.required_bytes(s) for s in specs)
+        rep = Server(be, hbm_budget=budget, chunk_steps=64, keep_moments=True).run(specs)
+        be.close()
+    summ = rep.summary()
+    print(summ)
+    assert summ["done"] == len(specs)
+    assert rep.peak_bytes <= budget
+    assert np.isfinite(rep.p50) and rep.p99 >= rep.p50
+    for s in specs[:4]:
+        alone = _batch_run([s])[0]
+        got = rep.results[s.job_id].moments
+        assert np.array_equal(got["u"], alone["u"]), s.job_id
