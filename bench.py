@@ -68,15 +68,33 @@ def read_traffic(kernel: str):
     return float(m.group(1)) if m else None
 
 
-def cpu_baseline(seconds_hint: float = 15.0):
-    """Time the FP64 CPU oracle on a bounded sample of the same workload."""
+def cpu_baseline(workload: str = "d3q19_tg", seconds_hint: float = 15.0):
+    """Time the FP64 CPU oracle on a bounded sample of the same workload: the
+    same lattice, flow and parameters on a smaller domain (the per-node work
+    does not depend on the domain size)."""
     import oracle
-    from paper_2304_06437_amd import inputs
 
-    n = 128
-    p = oracle.Params(lattice=19, nx=n, ny=n, nz=n, tau=0.55)
-    rho, u = inputs.taylor_green_3d(n, n, n, 0.02)
-    f = oracle.init(p, rho, u)
+    w = WORKLOADS[workload]
+    n = {9: 1024, 19: 128, 27: 96}[w["lattice"]]
+    if w["species"] == 2:
+        n = 96
+    shape = (n, n, 1) if w["lattice"] == 9 else (n, n, n)
+    kw = dict(lattice=w["lattice"], nx=shape[0], ny=shape[1], nz=shape[2], tau=w["tau"],
+              order=w["order"], species=w["species"])
+    if w["flow"] == "channel":
+        kw.update(force=(1e-6, 0.0, 0.0), bb=(0, 0, 1))
+    if w["species"] == 2:
+        kw.update(sigma=0.03, beta=0.7)
+    p = oracle.Params(**kw)
+    sub = dict(w, n=n)
+    if w["flow"] == "droplets":
+        from paper_2304_06437_amd import inputs
+
+        centres = inputs.droplet_centres(n, 3, 12.0, gap=2.0, seed=7)
+        rho, u, phi = inputs.droplets(n, centres, 12.0)
+    else:
+        rho, u, phi = workload_fields(sub, n)
+    f = oracle.init(p, rho, u, phi)
     t = time.perf_counter()
     oracle.run(p, f, 1)
     one = time.perf_counter() - t
@@ -84,13 +102,17 @@ def cpu_baseline(seconds_hint: float = 15.0):
     t = time.perf_counter()
     oracle.run(p, f, steps)
     dt = time.perf_counter() - t
+    nodes = shape[0] * shape[1] * shape[2]
     return {
-        "value": n ** 3 * steps / dt / 1e6,
+        "value": nodes * steps / dt / 1e6,
         "unit": "MLUPS",
         "cores": oracle.threads(),
         "kind": "oracle",
-        "sample": f"D3Q19 {n}^3 periodic Taylor-Green (u0 0.02, tau 0.55), FP64 two-array "
-                  f"oracle, {steps} steps ({dt:.1f} s); same per-node work as the 512^3 workload",
+        "sample": (w["desc"].format(n=n) if w["flow"] != "droplets" else
+                   f"two-species D3Q19 {n}^3 periodic, 3 droplets radius 12, tau 1.0, "
+                   "sigma 0.03, beta 0.7") +
+                  f"; FP64 two-array oracle, {steps} steps ({dt:.1f} s) on a {n}-edge "
+                  "domain; same per-node work as the benchmark",
     }
 
 
@@ -138,12 +160,47 @@ def copy_ceiling(torch, nbytes: int = 4 << 30, reps: int = 10):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
+# name -> problem statement (all synthetic, seeded)
+WORKLOADS = {
+    "d3q19_tg": dict(lattice=19, n=512, tau=0.55, flow="tg3d", order=2, species=1,
+                     desc="D3Q19 {n}^3 periodic 3D Taylor-Green (u0 0.02, tau 0.55, rho0 1)"),
+    "d3q19_channel": dict(lattice=19, n=256, tau=0.6, flow="channel", order=2, species=1,
+                          desc="D3Q19 {n}^3 channel: walls in z, periodic x/y, force 1e-6 along x, "
+                               "tau 0.6, rho 1 + 1e-4 seeded noise"),
+    "d3q27_tg3": dict(lattice=27, n=512, tau=0.55, flow="tg3d", order=3, species=1,
+                      desc="D3Q27 third-order Hermite {n}^3 periodic 3D Taylor-Green (u0 0.02, "
+                           "tau 0.55)"),
+    "two_species": dict(lattice=19, n=256, tau=1.0, flow="droplets", order=2, species=2,
+                        desc="two-species D3Q19 {n}^3 periodic, 64 droplets radius 12 at seeded "
+                             "non-overlapping positions, density ratio 1, tau 1.0, sigma 0.03, "
+                             "beta 0.7"),
+    "d2q9_tg": dict(lattice=9, n=4096, tau=0.8, flow="tg2d", order=2, species=1,
+                    desc="D2Q9 {n}^2 periodic 2D Taylor-Green (u0 0.01, tau 0.8)"),
+}
+
+
+def workload_fields(w, n):
+    from paper_2304_06437_amd import inputs
+
+    if w["flow"] == "tg3d":
+        return inputs.taylor_green_3d(n, n, n, 0.02) + (None,)
+    if w["flow"] == "tg2d":
+        return inputs.taylor_green_2d(n, n, 0.01) + (None,)
+    if w["flow"] == "channel":
+        return inputs.channel_noise(n, n, n, 3) + (None,)
+    if w["flow"] == "droplets":
+        centres = inputs.droplet_centres(n, 64, 12.0, gap=2.0, seed=7)
+        return inputs.droplets(n, centres, 12.0)
+    raise ValueError(w["flow"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=512, help="cube edge (512 is the workload)")
+    ap.add_argument("--workload", default="d3q19_tg", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0, help="domain edge (0: the workload's own)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "bf16s"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
@@ -163,18 +220,25 @@ def main():
     from paper_2304_06437_amd.sim import Simulation, make_params
 
     lb.load()
-    n = args.n
-    N = n ** 3
-    params = make_params(lattice=19, shape=(n, n, n), tau=0.55, storage=args.storage)
-    rho, u = inputs.taylor_green_3d(n, n, n, 0.02)
-
+    w = WORKLOADS[args.workload]
+    n = args.n or w["n"]
+    shape = (n, n, 1) if w["lattice"] == 9 else (n, n, n)
+    N = shape[0] * shape[1] * shape[2]
+    kw = dict(lattice=w["lattice"], shape=shape, tau=w["tau"], order=w["order"],
+              storage=args.storage, species=w["species"])
+    if w["flow"] == "channel":
+        kw.update(force=(1e-6, 0.0, 0.0), bc=(0, 0, 1))
+    if w["species"] == 2:
+        kw.update(sigma=0.03, beta=0.7)
+    params = make_params(**kw)
+    rho, u, phi = workload_fields(w, n)
     copy_gbs = copy_ms = None
     if not args.no_copy:
         copy_gbs, copy_ms = copy_ceiling(torch)
 
     sim = Simulation(params)
-    sim.init(rho, u)
-    del rho, u
+    sim.init(rho, u, phi)
+    del rho, u, phi
     sim.step(args.warmup)
     sim.synchronize()
 
@@ -192,13 +256,17 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     mlups = N * args.steps / elapsed / 1e6
     ssize = {"f32": 4, "f16s": 2, "bf16s": 2}[args.storage]
-    b1, b2 = algorithmic_bytes(19, 10, ssize, 4)
+    Q = w["lattice"]
+    D = 2 if Q == 9 else 3
+    M = 1 + D + D * (D + 1) // 2 + (1 if w["species"] == 2 else 0)
+    b1, b2 = algorithmic_bytes(Q * w["species"], M, ssize, 4)
     avg = [kms[i] / max(klaunch[i], 1) for i in range(2)]
     names = ["moments", "stream_collide"]
     dom = 0 if avg[0] > avg[1] else 1
     bytes_launch = [b1 * N, b2 * N]
     achieved = bytes_launch[dom] / (avg[dom] * 1e-3) / 1e9
-    traffic = read_traffic(names[dom]) if args.storage == "f32" and n == 512 else None
+    headline = args.workload == "d3q19_tg" and args.storage == "f32" and n == 512
+    traffic = read_traffic(names[dom]) if headline else None
 
     out = {
         "metric": METRIC,
@@ -214,10 +282,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"D3Q19 {n}^3 periodic 3D Taylor-Green (u0 0.02, tau 0.55, rho0 1), "
-                        f"{args.storage} population storage, f32 arithmetic",
-            "lattice": "D3Q19", "nodes": N, "storage": args.storage, "compute": "f32",
-            "bytes_per_update": b1 + b2,
+            "workload": w["desc"].format(n=n) + f", {args.storage} population storage, "
+                        "f32 arithmetic",
+            "name": args.workload, "lattice": f"D{D}Q{Q}", "nodes": N,
+            "storage": args.storage, "compute": "f32", "bytes_per_update": b1 + b2,
         },
         "roofline": {
             "bound": "hbm",
@@ -242,7 +310,7 @@ def main():
     if args.serve_jobs > 0:
         out["serving"] = serving(torch, args.serve_jobs, args.serve_rate, args.serve_budget_gb)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

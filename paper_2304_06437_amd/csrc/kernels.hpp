@@ -255,8 +255,6 @@ __device__ __forceinline__ void moments_body(const S* __restrict__ f, C* __restr
   C s[L::Q][V];
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
-  // keep every load in flight before the arithmetic starts
-  __builtin_amdgcn_sched_barrier(0);
   C out[ML::M][V];
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -420,7 +418,7 @@ struct StreamCollide {
 #pragma unroll
         for (int q = 0; q < M; ++q) {
           if (ln.act[h]) {
-            load_plain<C, E>(m + (int64_t)q * p.npad + ln.rowbase + ln.xh[h], mv[h][q]);
+            load_plain<C, E, false>(m + (int64_t)q * p.npad + ln.rowbase + ln.xh[h], mv[h][q]);
           } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) mv[h][q][e] = C(0);

@@ -19,42 +19,62 @@
 
 namespace lbk {
 
+// Lattice weights t_a and perturbation weights B_a as integers over one
+// denominator (t_a = tmul/den, B_a = bmul/den), so that the perturbation
+// and the colour split are formed with one rounding per node and their
+// lattice sums carry no fixed-sign error from rounded constants.
 template <class L>
 struct ColourWeights;
 
-// Reis & Phillips (2007) set for D2Q9.
+// Reis & Phillips (2007) set for D2Q9: B = (-4/27, 2/27, 5/108).
 template <>
 struct ColourWeights<D2Q9> {
-  static constexpr double B[9] = {-4.0 / 27.0,  2.0 / 27.0,  2.0 / 27.0,  2.0 / 27.0, 2.0 / 27.0,
-                                  5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0, 5.0 / 108.0};
+  static constexpr int den = 108;
+  static constexpr int tmul[9] = {48, 12, 12, 12, 12, 3, 3, 3, 3};
+  static constexpr int bmul[9] = {-16, 8, 8, 8, 8, 5, 5, 5, 5};
 };
 
-// Liu, Valocchi & Kang (2012) set for D3Q19.
+// Liu, Valocchi & Kang (2012) set for D3Q19: B = (-1/3, 1/18, 1/36).
 template <>
 struct ColourWeights<D3Q19> {
-  static constexpr double B[19] = {-1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
-                                   1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
-                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
-                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  static constexpr int den = 36;
+  static constexpr int tmul[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+  static constexpr int bmul[19] = {-12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
 };
+
+template <class L>
+constexpr bool colour_weights_consistent() {
+  int tsum = 0, bsum = 0;
+  for (int a = 0; a < L::Q; ++a) {
+    if (ColourWeights<L>::tmul[a] * L::wden != L::wmul[a] * ColourWeights<L>::den) return false;
+    tsum += ColourWeights<L>::tmul[a];
+    bsum += ColourWeights<L>::bmul[a];
+  }
+  // sum t = 1 and sum B = cs2
+  return tsum == ColourWeights<L>::den && 3 * bsum == ColourWeights<L>::den;
+}
+static_assert(colour_weights_consistent<D2Q9>(), "D2Q9 colour weights");
+static_assert(colour_weights_consistent<D3Q19>(), "D3Q19 colour weights");
 
 template <typename C>
 struct ColourParams {
-  C pert;   // (9/4) sigma omega
-  C beta;
+  C pert;   // (9/4) sigma omega / den
+  C beta;   // beta / den
 };
 
 // Per-node state carried along x in the two-species sweep:
-// post-collision coefficients of the mixture, then S = (9/4) sigma omega |G|,
-// the unit normal n (D), rho_R/rho and beta rho_R rho_B / rho.
+// post-collision coefficients of the mixture, then S = (9/4) sigma omega |G|
+// / den, the unit normal n (D), rho_R/rho, rho_R rho0 / (rho den) and
+// beta rho_R rho_B / (rho den).
 template <class L>
 struct ColourLayout {
   static constexpr int K = CoefLayout<L, 2>::K;
   static constexpr int S = K;
   static constexpr int N = K + 1;
   static constexpr int XR = K + 1 + L::D;
-  static constexpr int RB = K + 2 + L::D;
-  static constexpr int KT = K + 3 + L::D;
+  static constexpr int R0 = K + 2 + L::D;
+  static constexpr int RB = K + 3 + L::D;
+  static constexpr int KT = K + 4 + L::D;
 };
 
 // Moments sweep: mixture moments from set 0, red density from set 1, and
@@ -192,14 +212,20 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
     for (int al = 0; al < D; ++al) st[XL::N + al] = C(0);
   }
   st[XL::XR] = xr;
+  st[XL::R0] = scaled<1, ColourWeights<L>::den>(xr * p.rho0);
   st[XL::RB] = cp.beta * xr * xb * rho;
 }
 
 // Value of link A from a source node's state: (shifted mixture, red).
+//   g*_a  = [regularized mixture]_a + S' (tmul_a (c_a.n)^2 - bmul_a)
+//   f_R,a = (rho_R/rho) g*_a + tmul_a rho_R rho0/(rho den)
+//           + beta' tmul_a (c_a.n)/|c_a|
+// with S' = S/den and beta' = beta rho_R rho_B/(rho den); the unshifted red
+// population is (rho_R/rho)(g*_a + t_a rho0) + recolouring.
 template <class L, int A, typename C>
-__device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], const C rho0,
-                                            C& gs, C& fr) {
+__device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], C& gs, C& fr) {
   using XL = ColourLayout<L>;
+  using CW = ColourWeights<L>;
   constexpr int D = L::D;
   const C (&k)[XL::K] = *reinterpret_cast<const C(*)[XL::K]>(&st[0]);
   C g = link_value<L, 2, A, C>(k);
@@ -209,18 +235,17 @@ __device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], 
     if (L::c[A][al] > 0) cn += st[XL::N + al];
     if (L::c[A][al] < 0) cn -= st[XL::N + al];
   }
-  constexpr double t = L::w[A];
-  constexpr double Bw = ColourWeights<L>::B[A];
+  constexpr int tm = CW::tmul[A];
+  constexpr int bm = CW::bmul[A];
   constexpr int c2 = L::c[A][0] * L::c[A][0] + L::c[A][1] * L::c[A][1] + L::c[A][2] * L::c[A][2];
-  g += st[XL::S] * (C(t) * cn * cn - C(Bw));
-  const C gtot = g + C(t) * rho0;
+  g += st[XL::S] * (C(tm) * (cn * cn) - C(bm));
   C rec = C(0);
   if constexpr (c2 > 0) {
     constexpr double inv = c2 == 1 ? 1.0 : c2 == 2 ? 0.70710678118654752440 : 0.57735026918962576451;
-    rec = st[XL::RB] * C(t) * cn * C(inv);
+    rec = st[XL::RB] * (C(tm) * (cn * C(inv)));
   }
   gs = g;
-  fr = st[XL::XR] * gtot + rec;
+  fr = st[XL::XR] * g + C(tm) * st[XL::R0] + rec;
 }
 
 // Stream-collide for two species.  One wavefront per x-row segment of 64 E
@@ -258,13 +283,13 @@ struct StreamCollide2 {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if constexpr (cx == 0) {
-          colour_link<L, A, C>(own[e], p.rho0, gv[e], rv[e]);
+          colour_link<L, A, C>(own[e], gv[e], rv[e]);
         } else if constexpr (cx > 0) {
-          if (e > 0) colour_link<L, A, C>(own[e > 0 ? e - 1 : 0], p.rho0, gv[e], rv[e]);
-          else colour_link<L, A, C>(left, p.rho0, gv[e], rv[e]);
+          if (e > 0) colour_link<L, A, C>(own[e > 0 ? e - 1 : 0], gv[e], rv[e]);
+          else colour_link<L, A, C>(left, gv[e], rv[e]);
         } else {
-          if (e < E - 1) colour_link<L, A, C>(own[e < E - 1 ? e + 1 : 0], p.rho0, gv[e], rv[e]);
-          else colour_link<L, A, C>(right, p.rho0, gv[e], rv[e]);
+          if (e < E - 1) colour_link<L, A, C>(own[e < E - 1 ? e + 1 : 0], gv[e], rv[e]);
+          else colour_link<L, A, C>(right, gv[e], rv[e]);
         }
       }
       const int64_t t = p.nx * (ty + p.ny * tz) + xs;
@@ -284,7 +309,7 @@ struct StreamCollide2 {
     } else {
       C gv[E], rv[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], p.rho0, gv[e], rv[e]);
+      for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], gv[e], rv[e]);
       store_pack<S, C, E>(f + (int64_t)AB * p.npad + rowbase + xs, gv);
       store_pack<S, C, E>(f + (int64_t)(L::Q + AB) * p.npad + rowbase + xs, rv);
     }
@@ -296,8 +321,8 @@ struct StreamCollide2 {
         if (cx < 0 && xs == 0) { e = 0; xw = 0; }
         if (e >= 0) {
           C g, r;
-          if (e == 0) colour_link<L, A, C>(own[0], p.rho0, g, r);
-          else colour_link<L, A, C>(own[E - 1], p.rho0, g, r);
+          if (e == 0) colour_link<L, A, C>(own[0], g, r);
+          else colour_link<L, A, C>(own[E - 1], g, r);
           f[(int64_t)AB * p.npad + rowbase + xw] = Codec<S, C>::store(g);
           f[(int64_t)(L::Q + AB) * p.npad + rowbase + xw] = Codec<S, C>::store(r);
         }
@@ -339,12 +364,12 @@ struct StreamCollide2 {
       C mv[M][E];
 #pragma unroll
       for (int q = 0; q < M; ++q) {
-        if (act) load_plain<C, E>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
+        if (act) load_plain<C, E, false>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
         else
 #pragma unroll
           for (int e = 0; e < E; ++e) mv[q][e] = C(0);
       }
-      if (act) load_plain<C, E>(phi + rowbase + xs, phio);
+      if (act) load_plain<C, E, false>(phi + rowbase + xs, phio);
       else
 #pragma unroll
         for (int e = 0; e < E; ++e) phio[e] = C(0);
@@ -361,6 +386,7 @@ struct StreamCollide2 {
         const C xr = (C(1) + phio[e]) * C(0.5);
         const C xb = (C(1) - phio[e]) * C(0.5);
         own[e][XL::XR] = xr;
+        own[e][XL::R0] = scaled<1, ColourWeights<L>::den>(xr * p.rho0);
         own[e][XL::RB] = cp.beta * xr * xb * rho;
       }
     }
@@ -395,7 +421,7 @@ struct StreamCollide2 {
         const int64_t tb = p.nx * (ty + p.ny * tz);
         C pv[E];
         if (inside) {
-          if (act) load_plain<C, E>(phi + tb + xs, pv);
+          if (act) load_plain<C, E, false>(phi + tb + xs, pv);
           else
 #pragma unroll
             for (int e = 0; e < E; ++e) pv[e] = C(0);

@@ -233,9 +233,12 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
     h->partial = (double*)((char*)h->base + h->L.r_off);
     fill_params(h->p32, p, h->L, h->v2);
     fill_params(h->p64, p, h->L, h->v2);
-    const double pert = 2.25 * p->sigma / p->tau;  // (9/4) sigma omega
-    h->cp32 = {(float)pert, (float)p->beta};
-    h->cp64 = {pert, p->beta};
+    // (9/4) sigma omega and beta over the colour-weight denominator
+    const double cden = p->lattice == LB_D2Q9 ? 108.0 : 36.0;
+    const double pert = 2.25 * p->sigma / p->tau / cden;
+    const double beta = p->beta / cden;
+    h->cp32 = {(float)pert, (float)beta};
+    h->cp64 = {pert, beta};
     hipError_t e = hipMemsetAsync(h->base, 0, h->L.total, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {

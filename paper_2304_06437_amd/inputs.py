@@ -124,14 +124,17 @@ def droplet_centres(n: int, count: int, radius: float, gap: float = 2.0, seed: i
 
 def droplets(n: int, centres, radius: float, rho0: float = 1.0):
     """phi = +1 inside any sphere (periodic minimum image), -1 outside; rest."""
-    x, y, z = _grid(n, n, n)
-    phi = -np.ones(n ** 3)
+    phi = -np.ones((n, n, n))
+    r = int(math.ceil(radius)) + 1
+    off = np.arange(-r, r + 1)
     for c in centres:
-        dx = np.abs(x - c[0]); dx = np.minimum(dx, n - dx)
-        dy = np.abs(y - c[1]); dy = np.minimum(dy, n - dy)
-        dz = np.abs(z - c[2]); dz = np.minimum(dz, n - dz)
-        phi[dx * dx + dy * dy + dz * dz <= radius * radius] = 1.0
-    return np.full(n ** 3, rho0), np.zeros((3, n ** 3)), phi
+        base = np.floor(np.asarray(c)).astype(np.int64)
+        ix, iy, iz = base[0] + off, base[1] + off, base[2] + off
+        dz, dy, dx = np.meshgrid(iz - c[2], iy - c[1], ix - c[0], indexing="ij")
+        inside = dx * dx + dy * dy + dz * dz <= radius * radius
+        zz, yy, xx = np.meshgrid(iz % n, iy % n, ix % n, indexing="ij")
+        phi[zz[inside], yy[inside], xx[inside]] = 1.0
+    return np.full(n ** 3, rho0), np.zeros((3, n ** 3)), phi.reshape(-1)
 
 
 def random_state(N: int, D: int, seed: int, drho: float = 1e-2, du: float = 0.05,
