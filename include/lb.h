@@ -133,6 +133,20 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
  * boundaries) on the handle's stream and return without waiting. */
 int lb_step(lb_handle* h, int64_t nsteps);
 
+/* Enqueue one half of a time step: which = 0 the moments sweep (reads the
+ * populations, writes the moment arrays), which = 1 the fused
+ * stream-collide sweep (reads the moment arrays only, rewrites every
+ * population in place).  lb_step(h, 1) is lb_sweep(h, 0) then
+ * lb_sweep(h, 1); the step counter advances after which = 1.  For
+ * instrumentation and for tests of the sweeps' data dependencies. */
+int lb_sweep(lb_handle* h, int which);
+
+/* Device layout of the handle's state, for tests and tools: byte offsets of
+ * the population and moment arrays from the start of the device buffer and
+ * the element stride between consecutive arrays. */
+int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
+              int64_t* array_stride);
+
 /* Wait for all work enqueued on the handle's stream. */
 int lb_synchronize(lb_handle* h);
 

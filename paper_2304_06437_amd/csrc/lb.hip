@@ -314,6 +314,25 @@ int lb_step(lb_handle* h, int64_t nsteps) {
   return LB_OK;
 }
 
+int lb_sweep(lb_handle* h, int which) {
+  if (!h || (which != 0 && which != 1)) return LB_EINVAL;
+  if (which == 0) LB_TRY_HIP(h->impl->moments(h));
+  else {
+    LB_TRY_HIP(h->impl->stream_collide(h));
+    ++h->steps;
+  }
+  return LB_OK;
+}
+
+int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
+              int64_t* array_stride) {
+  if (!h || !pop_offset || !moment_offset || !array_stride) return LB_EINVAL;
+  *pop_offset = h->L.f_off;
+  *moment_offset = h->L.m_off;
+  *array_stride = h->L.npad;
+  return LB_OK;
+}
+
 int lb_synchronize(lb_handle* h) {
   if (!h) return LB_EINVAL;
   return launch_status(hipStreamSynchronize(h->stream));

@@ -46,19 +46,24 @@ def _grid(nx, ny, nz):
     return x.reshape(-1), y.reshape(-1), z.reshape(-1)
 
 
+def _axis(n):
+    return np.arange(n, dtype=np.float64)
+
+
 def taylor_green_2d(nx: int, ny: int, u0: float, rho0: float = 1.0):
     """2D Taylor-Green vortex with its pressure field (rho = rho0 + 3 p).
 
     u_x = -u0 cos(kx x) sin(ky y), u_y = u0 (kx/ky) sin(kx x) cos(ky y),
     p = -(rho0 u0^2 / 4) (cos 2kx x + (kx/ky)^2 cos 2ky y).
+    Built from 1D factors broadcast over the grid.
     """
     kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
-    x, y, _ = _grid(nx, ny, 1)
+    x, y = _axis(nx)[None, :], _axis(ny)[:, None]
     r = kx / ky
     ux = -u0 * np.cos(kx * x) * np.sin(ky * y)
     uy = u0 * r * np.sin(kx * x) * np.cos(ky * y)
     p = -(rho0 * u0 * u0 / 4.0) * (np.cos(2 * kx * x) + r * r * np.cos(2 * ky * y))
-    return rho0 + 3.0 * p, np.stack([ux, uy])
+    return (rho0 + 3.0 * p).reshape(-1), np.stack([ux.reshape(-1), uy.reshape(-1)])
 
 
 def taylor_green_3d(nx: int, ny: int, nz: int, u0: float, rho0: float = 1.0):
@@ -66,15 +71,20 @@ def taylor_green_3d(nx: int, ny: int, nz: int, u0: float, rho0: float = 1.0):
 
     u = u0 sin kx cos ky cos kz, v = -u0 cos kx sin ky cos kz, w = 0,
     rho = rho0 + (3 u0^2 / 16)(cos 2kx + cos 2ky)(cos 2kz + 2).
+    Built from 1D factors broadcast over the grid.
     """
     kx, ky, kz = 2 * math.pi / nx, 2 * math.pi / ny, 2 * math.pi / nz
-    x, y, z = _grid(nx, ny, nz)
-    ux = u0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
-    uy = -u0 * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
-    uz = np.zeros_like(ux)
-    rho = rho0 + (3.0 * u0 * u0 / 16.0) * (np.cos(2 * kx * x) + np.cos(2 * ky * y)) * (
-        np.cos(2 * kz * z) + 2.0)
-    return rho, np.stack([ux, uy, uz])
+    x = _axis(nx)[None, None, :]
+    y = _axis(ny)[None, :, None]
+    z = _axis(nz)[:, None, None]
+    N = nx * ny * nz
+    u = np.empty((3, N))
+    u[0] = (u0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)).reshape(-1)
+    u[1] = (-u0 * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)).reshape(-1)
+    u[2] = 0.0
+    rho = (rho0 + (3.0 * u0 * u0 / 16.0) * (np.cos(2 * kx * x) + np.cos(2 * ky * y)) * (
+        np.cos(2 * kz * z) + 2.0)).reshape(-1)
+    return rho, u
 
 
 def shear_wave(nx: int, ny: int, nz: int, D: int, u0: float, axis_u: int = 0,

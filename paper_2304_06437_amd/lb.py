@@ -87,6 +87,9 @@ def load():
     lib.lb_timing_begin.argtypes = [H, ctypes.c_int64]
     lib.lb_timing_end.argtypes = [H, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.lb_sweep.argtypes = [H, ctypes.c_int]
+    lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(ctypes.c_int64)]
     lib.lb_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.lb_batch_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -154,6 +157,17 @@ def lb_init(h, rho, u, phi=None):
 
 def lb_step(h, nsteps: int):
     _check(load().lb_step(h, int(nsteps)), "lb_step")
+
+
+def lb_sweep(h, which: int):
+    _check(load().lb_sweep(h, int(which)), "lb_sweep")
+
+
+def lb_layout(h):
+    """(population byte offset, moment byte offset, element stride between arrays)."""
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
+    _check(load().lb_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "lb_layout")
+    return a.value, b.value, c.value
 
 
 def lb_synchronize(h):

@@ -25,6 +25,7 @@ from __future__ import annotations
 import math
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -163,11 +164,15 @@ class GpuBackend:
             raise ValueError(f"invalid request {spec}")
         return n
 
-    def create(self, spec: JobSpec):
+    def prepare(self, spec: JobSpec):
+        """Host-side initial fields (runs on the server's worker thread)."""
+        return spec.fields()
+
+    def create(self, spec: JobSpec, prepared=None):
         from .sim import Simulation
 
         sim = Simulation(self.params(spec), device=self.device, stream=self.stream)
-        rho, u = spec.fields()
+        rho, u = prepared if prepared is not None else spec.fields()
         sim.init(rho, u)
         return sim
 
@@ -202,10 +207,20 @@ class Server:
         self.sleep = sleep
 
     def run(self, specs) -> ServeReport:
+        prep = getattr(self.backend, "prepare", None)
+        pool = ThreadPoolExecutor(max_workers=2) if prep is not None else None
+        try:
+            return self._run(specs, pool, prep)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True, cancel_futures=True)
+
+    def _run(self, specs, pool, prep) -> ServeReport:
         pending = deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
         queue: deque = deque()
         active: list = []
         results = {}
+        futures = {}
         used = peak = 0
         max_active = chunks = 0
         t0 = self.clock()
@@ -216,7 +231,11 @@ class Server:
         while pending or queue or active:
             t = now()
             while pending and pending[0].arrival <= t:
-                queue.append(pending.popleft())
+                spec = pending.popleft()
+                queue.append(spec)
+                if pool is not None:
+                    # host-side preparation overlaps the GPU work of the running chunk
+                    futures[spec.job_id] = pool.submit(prep, spec)
             # admission: arrival order, as long as the head of the queue fits
             while queue and len(active) < self.max_active:
                 spec = queue[0]
@@ -227,8 +246,10 @@ class Server:
                     queue.popleft()
                     res.status, res.error = "rejected", str(e)
                     results[spec.job_id] = res
+                    futures.pop(spec.job_id, None)
                     continue
                 if need > self.budget:
+                    futures.pop(spec.job_id, None)
                     queue.popleft()
                     res.status, res.error = "rejected", f"needs {need} B > budget {self.budget} B"
                     results[spec.job_id] = res
@@ -238,7 +259,11 @@ class Server:
                 queue.popleft()
                 res.admitted = now()
                 try:
-                    handle = self.backend.create(spec)
+                    fut = futures.pop(spec.job_id, None)
+                    if fut is not None:
+                        handle = self.backend.create(spec, fut.result())
+                    else:
+                        handle = self.backend.create(spec)
                 except Exception as e:
                     res.status, res.error, res.finished = "failed", repr(e), now()
                     results[spec.job_id] = res
