@@ -141,11 +141,17 @@ int lb_step(lb_handle* h, int64_t nsteps);
  * instrumentation and for tests of the sweeps' data dependencies. */
 int lb_sweep(lb_handle* h, int which);
 
-/* Device layout of the handle's state, for tests and tools: byte offsets of
- * the population and moment arrays from the start of the device buffer and
- * the element stride between consecutive arrays. */
+/* Device layout of the handle's state, for tests and tools.  The population
+ * region (species*Q arrays of the storage type: set 0 then set 1) starts at
+ * byte pop_offset of the device buffer, the moment region (M arrays of the
+ * compute type: drho, j, Pi^neq [, phi]) at moment_offset.  Both are blocked
+ * structures of arrays over padded_nodes >= N nodes: with B = block_nodes (a
+ * power of two), element (a, n) of a region of NA arrays is element
+ * (n / B) * NA * B + a * B + n % B of that region.  Populations are stored
+ * shifted (f_a - t_a rho0 for set 0).  The layout is internal: it may change
+ * between versions, and only the moments are part of the interface. */
 int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
-              int64_t* array_stride);
+              int64_t* block_nodes, int64_t* padded_nodes);
 
 /* Wait for all work enqueued on the handle's stream. */
 int lb_synchronize(lb_handle* h);

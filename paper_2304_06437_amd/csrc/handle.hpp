@@ -21,6 +21,7 @@ struct Layout {
   int Q = 0, D = 0, M = 0, species = 1;
   size_t ssize = 0, csize = 0;  // bytes per stored population / per moment
   int64_t N = 0, npad = 0;
+  int lb = 10;                  // log2 of the block size of the array layout
   size_t f_off = 0, m_off = 0, r_off = 0, total = 0;
 };
 

@@ -41,16 +41,36 @@ namespace lbk {
 template <typename C>
 struct StepParams {
   int64_t nx, ny, nz;
-  int64_t npad;        // elements between consecutive arrays
+  int64_t npad;        // padded node count (a multiple of the block size)
   int64_t nseg;        // row segments per x-row in stream_collide
   int32_t bbx, bby, bbz;
-  int32_t pad_;
+  int32_t lb;          // log2 of the block size B (nodes)
   C rho0, inv_rho0;
   C F[3];
   C halfF[3];
   C omw;               // 1 - omega
   C omhw;              // 1 - omega/2
 };
+
+// -------------------------------------------------------------------------
+// Blocked array layout.  The padded node range [0, npad) is cut into blocks of
+// B = 2^lb consecutive nodes; a region of NA arrays stores, block after
+// block, B elements of array 0, then B of array 1, and so on:
+//   element (a, n) = (n >> lb) NA B + a B + (n & (B - 1)).
+// The NA streams a sweep touches at one time then lie inside one contiguous
+// NA B span instead of npad apart (plain structure of arrays), which the HBM
+// system serves faster.  B is a power of two >= 1024, so a vector of up to
+// 16 nodes that starts at a multiple of its length never crosses a block.
+// -------------------------------------------------------------------------
+template <int NA, typename C>
+__device__ __forceinline__ int64_t slot(const StepParams<C>& p, int64_t n) {
+  return (((n >> p.lb) * NA) << p.lb) + (n & ((int64_t(1) << p.lb) - 1));
+}
+
+template <typename C>
+__device__ __forceinline__ int64_t astride(const StepParams<C>& p) {
+  return int64_t(1) << p.lb;
+}
 
 // -------------------------------------------------------------------------
 // Node-level arithmetic.
@@ -252,9 +272,10 @@ __device__ __forceinline__ void moments_body(const S* __restrict__ f, C* __restr
                                              const StepParams<C>& p, int64_t i0) {
   using ML = MomentLayout<L>;
   if (i0 >= p.npad) return;
+  const int64_t B = astride(p), fs = slot<L::Q>(p, i0), ms = slot<ML::M>(p, i0);
   C s[L::Q][V];
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
+  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + fs + a * B, s[a]);
   C out[ML::M][V];
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -266,7 +287,7 @@ __device__ __forceinline__ void moments_body(const S* __restrict__ f, C* __restr
     for (int q = 0; q < ML::M; ++q) out[q][e] = me[q];
   }
 #pragma unroll
-  for (int q = 0; q < ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+  for (int q = 0; q < ML::M; ++q) store_plain<C, V>(m + ms + q * B, out[q]);
 }
 
 template <class L, typename S, typename C, int V>
@@ -339,7 +360,7 @@ struct StreamCollide {
                                  : link_value<L, ORDER, A, C>(right[h]);
           }
         }
-        S* dst = f + (int64_t)A * p.npad + trow + xs;
+        S* dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
         const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
         const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);    // source x = nx
         if (!(cut_lo || cut_hi)) {
@@ -357,15 +378,15 @@ struct StreamCollide {
         C bv[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) bv[e] = link_value<L, ORDER, A, C>(own[h][e]);
-        store_pack<S, C, E>(f + (int64_t)AB * p.npad + ln.rowbase + xs, bv);
+        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
       }
       if constexpr (cx != 0) {
         if (row_in && p.bbx) {
           if (cx > 0 && xs + E == p.nx)
-            f[(int64_t)AB * p.npad + ln.rowbase + p.nx - 1] =
+            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + AB * astride(p)] =
                 Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][E - 1]));
           if (cx < 0 && xs == 0)
-            f[(int64_t)AB * p.npad + ln.rowbase] =
+            f[slot<L::Q>(p, ln.rowbase) + AB * astride(p)] =
                 Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][0]));
         }
       }
@@ -385,8 +406,9 @@ struct StreamCollide {
   __device__ static void load_coef(const C* __restrict__ m, const StepParams<C>& p, int64_t idx,
                                    C (&k)[K]) {
     C mm[M];
+    const int64_t ms = slot<M>(p, idx);
 #pragma unroll
-    for (int q = 0; q < M; ++q) mm[q] = m[(int64_t)q * p.npad + idx];
+    for (int q = 0; q < M; ++q) mm[q] = m[ms + q * astride(p)];
     post_collision<L, ORDER, C>(mm, p, k);
   }
 
@@ -418,7 +440,7 @@ struct StreamCollide {
 #pragma unroll
         for (int q = 0; q < M; ++q) {
           if (ln.act[h]) {
-            load_plain<C, E, false>(m + (int64_t)q * p.npad + ln.rowbase + ln.xh[h], mv[h][q]);
+            load_plain<C, E, false>(m + slot<M>(p, ln.rowbase + ln.xh[h]) + q * astride(p), mv[h][q]);
           } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) mv[h][q][e] = C(0);
@@ -497,11 +519,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
 // stage holds (1 + D) x cnt doubles: drho, then u.
 // -------------------------------------------------------------------------
 template <class L, int ORDER, typename S, typename C, int A>
-__device__ __forceinline__ void init_links(S* __restrict__ f, int64_t npad, int64_t n,
+__device__ __forceinline__ void init_links(S* __restrict__ f, int64_t B, int64_t fs,
                                            const C (&k)[CoefLayout<L, ORDER>::K]) {
   if constexpr (A < L::Q) {
-    f[(int64_t)A * npad + n] = Codec<S, C>::store(link_value<L, ORDER, A, C>(k));
-    init_links<L, ORDER, S, C, A + 1>(f, npad, n, k);
+    f[fs + A * B] = Codec<S, C>::store(link_value<L, ORDER, A, C>(k));
+    init_links<L, ORDER, S, C, A + 1>(f, B, fs, k);
   }
 }
 
@@ -526,7 +548,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ stage, 
   }
   C k[CL::K];
   post_collision<L, ORDER, C>(mm, q, k);
-  init_links<L, ORDER, S, C, 0>(f, p.npad, n0 + i, k);
+  init_links<L, ORDER, S, C, 0>(f, astride(p), slot<L::Q>(p, n0 + i), k);
 }
 
 // -------------------------------------------------------------------------
@@ -542,8 +564,9 @@ __global__ __launch_bounds__(256) void k_readout(const S* __restrict__ f, double
   if (i >= cnt) return;
   const int64_t n = n0 + i;
   C s[L::Q], me[ML::M];
+  const int64_t fs = slot<L::Q>(p, n);
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) s[a] = Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+  for (int a = 0; a < L::Q; ++a) s[a] = Codec<S, C>::load(f[fs + a * astride(p)]);
   node_moments<L, C>(s, p, me);
   out[i] = (double)p.rho0 + (double)me[ML::RHO];  // keep the deviation's digits
 #pragma unroll
@@ -566,9 +589,10 @@ __global__ __launch_bounds__(256) void k_conserved(const S* __restrict__ f,
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+    const int64_t fs = slot<L::Q>(p, n);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
-      const double s = (double)Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+      const double s = (double)Codec<S, C>::load(f[fs + a * astride(p)]);
       acc[0] += s;
 #pragma unroll
       for (int al = 0; al < 3; ++al) {

@@ -84,16 +84,18 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
                                               const StepParams<C>& p, int64_t i0) {
   using ML = MomentLayout<L>;
   if (i0 >= p.npad) return;
+  // population region: 2Q arrays (set 0, then set 1); moment region: M + 1
+  const int64_t B = astride(p), fs = slot<2 * L::Q>(p, i0), ms = slot<ML::M + 1>(p, i0);
   C s[L::Q][V];
   C rr[V];
 #pragma unroll
-  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + (int64_t)a * p.npad + i0, s[a]);
+  for (int a = 0; a < L::Q; ++a) load_pack<S, C, V>(f + fs + a * B, s[a]);
 #pragma unroll
   for (int e = 0; e < V; ++e) rr[e] = C(0);
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) {
     C r[V];
-    load_pack<S, C, V>(f + (int64_t)(L::Q + a) * p.npad + i0, r);
+    load_pack<S, C, V>(f + fs + (L::Q + a) * B, r);
 #pragma unroll
     for (int e = 0; e < V; ++e) rr[e] += r[e];
   }
@@ -110,7 +112,7 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
     out[ML::M][e] = (C(2) * rr[e] - rho) / rho;
   }
 #pragma unroll
-  for (int q = 0; q <= ML::M; ++q) store_plain<C, V>(m + (int64_t)q * p.npad + i0, out[q]);
+  for (int q = 0; q <= ML::M; ++q) store_plain<C, V>(m + ms + q * B, out[q]);
 }
 
 template <class L, typename S, typename C, int V>
@@ -119,17 +121,23 @@ __global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __
   moments2_body<L, S, C, V>(f, m, p, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V);
 }
 
+// Index of the phase field of node n: the last of the M + 1 moment arrays.
+template <class L, typename C>
+__device__ __forceinline__ int64_t phi_index(const StepParams<C>& p, int64_t n) {
+  return slot<MomentLayout<L>::M + 1>(p, n) + MomentLayout<L>::M * astride(p);
+}
+
 // Phase field of node (x + dx, ty, tz) given the wrapped/validated row
 // (ty, tz): x wraps for periodic x; beyond an x wall the node's own phi.
-template <typename C>
-__device__ __forceinline__ C phi_at(const C* __restrict__ phi, const StepParams<C>& p,
+template <class L, typename C>
+__device__ __forceinline__ C phi_at(const C* __restrict__ m, const StepParams<C>& p,
                                     int64_t trow_base, int64_t x, int dx, C own) {
   int64_t xx = x + dx;
   if (xx < 0 || xx >= p.nx) {
     if (p.bbx) return own;
     xx = (xx < 0) ? p.nx - 1 : 0;
   }
-  return phi[trow_base + xx];
+  return m[phi_index<L>(p, trow_base + xx)];
 }
 
 // Full per-node state of node (x, y, z) by scalar loads (segment halos).
@@ -143,13 +151,12 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
   const int64_t n = x + p.nx * (y + p.ny * z);
   C mm[ML::M];
 #pragma unroll
-  for (int q = 0; q < ML::M; ++q) mm[q] = m[(int64_t)q * p.npad + n];
+  for (int q = 0; q < ML::M; ++q) mm[q] = m[slot<ML::M + 1>(p, n) + q * astride(p)];
   C k[XL::K];
   post_collision<L, 2, C>(mm, p, k);
 #pragma unroll
   for (int q = 0; q < XL::K; ++q) st[q] = k[q];
-  const C* phi = m + (int64_t)ML::M * p.npad;
-  const C own = phi[n];
+  const C own = m[phi_index<L>(p, n)];
   // same row-by-row summation order as the vector path in StreamCollide2
   C G[3] = {C(0), C(0), C(0)};
 #pragma unroll
@@ -179,7 +186,7 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         if (!has[dx + 1]) continue;
-        const C v = inside ? phi_at<C>(phi, p, tb, x, dx, own) : own;
+        const C v = inside ? phi_at<L, C>(m, p, tb, x, dx, own) : own;
         const C wv = C(wm[dx + 1]) * v;
         if (dx > 0) G[0] += wv;
         if (dx < 0) G[0] -= wv;
@@ -276,8 +283,8 @@ struct StreamCollide2 {
       if (p.bbz) row_in = false;
       else tz = (tz < 0) ? p.nz - 1 : 0;
     }
-    S* fr0 = f + (int64_t)A * p.npad;
-    S* fr1 = f + (int64_t)(L::Q + A) * p.npad;
+    S* fr0 = f + A * astride(p);
+    S* fr1 = f + (L::Q + A) * astride(p);
     if (row_in) {
       C gv[E], rv[E];
 #pragma unroll
@@ -292,7 +299,8 @@ struct StreamCollide2 {
           else colour_link<L, A, C>(right, gv[e], rv[e]);
         }
       }
-      const int64_t t = p.nx * (ty + p.ny * tz) + xs;
+      // the E nodes from t on lie in one block
+      const int64_t t = slot<2 * L::Q>(p, p.nx * (ty + p.ny * tz) + xs);
       const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);
       const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);
       if (!(cut_lo || cut_hi)) {
@@ -310,8 +318,9 @@ struct StreamCollide2 {
       C gv[E], rv[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], gv[e], rv[e]);
-      store_pack<S, C, E>(f + (int64_t)AB * p.npad + rowbase + xs, gv);
-      store_pack<S, C, E>(f + (int64_t)(L::Q + AB) * p.npad + rowbase + xs, rv);
+      const int64_t t = slot<2 * L::Q>(p, rowbase + xs);
+      store_pack<S, C, E>(f + t + AB * astride(p), gv);
+      store_pack<S, C, E>(f + t + (L::Q + AB) * astride(p), rv);
     }
     if constexpr (cx != 0) {
       if (row_in && p.bbx) {
@@ -323,8 +332,9 @@ struct StreamCollide2 {
           C g, r;
           if (e == 0) colour_link<L, A, C>(own[0], g, r);
           else colour_link<L, A, C>(own[E - 1], g, r);
-          f[(int64_t)AB * p.npad + rowbase + xw] = Codec<S, C>::store(g);
-          f[(int64_t)(L::Q + AB) * p.npad + rowbase + xw] = Codec<S, C>::store(r);
+          const int64_t t = slot<2 * L::Q>(p, rowbase + xw);
+          f[t + AB * astride(p)] = Codec<S, C>::store(g);
+          f[t + (L::Q + AB) * astride(p)] = Codec<S, C>::store(r);
         }
       }
     }
@@ -356,7 +366,6 @@ struct StreamCollide2 {
     const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
     const int64_t xs = x0 + (int64_t)lane * E;
     const bool act = xs < p.nx;
-    const C* phi = m + (int64_t)M * p.npad;
 
     C own[E][KT];
     C phio[E];
@@ -364,12 +373,12 @@ struct StreamCollide2 {
       C mv[M][E];
 #pragma unroll
       for (int q = 0; q < M; ++q) {
-        if (act) load_plain<C, E, false>(m + (int64_t)q * p.npad + rowbase + xs, mv[q]);
+        if (act) load_plain<C, E, false>(m + slot<M + 1>(p, rowbase + xs) + q * astride(p), mv[q]);
         else
 #pragma unroll
           for (int e = 0; e < E; ++e) mv[q][e] = C(0);
       }
-      if (act) load_plain<C, E, false>(phi + rowbase + xs, phio);
+      if (act) load_plain<C, E, false>(m + phi_index<L>(p, rowbase + xs), phio);
       else
 #pragma unroll
         for (int e = 0; e < E; ++e) phio[e] = C(0);
@@ -421,7 +430,7 @@ struct StreamCollide2 {
         const int64_t tb = p.nx * (ty + p.ny * tz);
         C pv[E];
         if (inside) {
-          if (act) load_plain<C, E, false>(phi + tb + xs, pv);
+          if (act) load_plain<C, E, false>(m + phi_index<L>(p, tb + xs), pv);
           else
 #pragma unroll
             for (int e = 0; e < E; ++e) pv[e] = C(0);
@@ -433,8 +442,8 @@ struct StreamCollide2 {
         C pl = lane_from_below(pv[E - 1]);
         C pr = lane_from_above(pv[0]);
         if (inside) {
-          if (lane == 0) pl = phi_at<C>(phi, p, tb, x0, -1, phio[0]);
-          if (act && xs + E == xend) pr = phi_at<C>(phi, p, tb, xend - 1, 1, phio[E - 1]);
+          if (lane == 0) pl = phi_at<L, C>(m, p, tb, x0, -1, phio[0]);
+          if (act && xs + E == xend) pr = phi_at<L, C>(m, p, tb, xend - 1, 1, phio[E - 1]);
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -535,13 +544,13 @@ __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m
 // Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.
 // stage: (2 + D) x cnt doubles: drho, u, phi.
 template <class L, typename S, typename C, int A>
-__device__ __forceinline__ void init2_links(S* __restrict__ f, int64_t npad, int64_t n,
+__device__ __forceinline__ void init2_links(S* __restrict__ f, int64_t B, int64_t fs,
                                             const C (&k)[CoefLayout<L, 2>::K], C rho0, C xr) {
   if constexpr (A < L::Q) {
     const C s = link_value<L, 2, A, C>(k);
-    f[(int64_t)A * npad + n] = Codec<S, C>::store(s);
-    f[(int64_t)(L::Q + A) * npad + n] = Codec<S, C>::store(xr * (s + C(L::w[A]) * rho0));
-    init2_links<L, S, C, A + 1>(f, npad, n, k, rho0, xr);
+    f[fs + A * B] = Codec<S, C>::store(s);
+    f[fs + (L::Q + A) * B] = Codec<S, C>::store(xr * (s + C(L::w[A]) * rho0));
+    init2_links<L, S, C, A + 1>(f, B, fs, k, rho0, xr);
   }
 }
 
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage,
   }
   C k[CoefLayout<L, 2>::K];
   post_collision<L, 2, C>(mm, q, k);
-  init2_links<L, S, C, 0>(f, p.npad, n0 + i, k, p.rho0, xr);
+  init2_links<L, S, C, 0>(f, astride(p), slot<2 * L::Q>(p, n0 + i), k, p.rho0, xr);
 }
 
 // Read-out: rho, u, Pi^neq of the mixture and phi; (2 + D + D(D+1)/2) x cnt.
@@ -580,10 +589,11 @@ __global__ __launch_bounds__(256) void k_readout2(const S* __restrict__ f, doubl
   const int64_t n = n0 + i;
   C s[L::Q], me[ML::M];
   C rr = C(0);
+  const int64_t fs = slot<2 * L::Q>(p, n);
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) {
-    s[a] = Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
-    rr += Codec<S, C>::load(f[(int64_t)(L::Q + a) * p.npad + n]);
+    s[a] = Codec<S, C>::load(f[fs + a * astride(p)]);
+    rr += Codec<S, C>::load(f[fs + (L::Q + a) * astride(p)]);
   }
   node_moments<L, C>(s, p, me);
   const C rho = p.rho0 + me[ML::RHO];
@@ -606,16 +616,17 @@ __global__ __launch_bounds__(256) void k_conserved2(const S* __restrict__ f,
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+    const int64_t fs = slot<2 * L::Q>(p, n);
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
-      const double s = (double)Codec<S, C>::load(f[(int64_t)a * p.npad + n]);
+      const double s = (double)Codec<S, C>::load(f[fs + a * astride(p)]);
       acc[0] += s;
 #pragma unroll
       for (int al = 0; al < 3; ++al) {
         if (L::c[a][al] > 0) acc[1 + al] += s;
         if (L::c[a][al] < 0) acc[1 + al] -= s;
       }
-      acc[4] += (double)Codec<S, C>::load(f[(int64_t)(L::Q + a) * p.npad + n]);
+      acc[4] += (double)Codec<S, C>::load(f[fs + (L::Q + a) * astride(p)]);
     }
   }
 #pragma unroll

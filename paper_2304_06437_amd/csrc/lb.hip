@@ -5,8 +5,13 @@
 //      species), or the mixture g_a - t_a rho0 and the red f_R,a (two)
 //   m  M moment arrays (drho, j, Pi^neq, and phi for two species), compute type
 //   r  FP64 partial sums of the conservation reduction
-// Every array holds npad >= N elements (npad a multiple of 4096), so every
-// array starts 256-byte aligned and the moments sweep needs no tail.
+// Both regions are blocked structures of arrays: the node range, padded to
+// npad (a multiple of the block size B, a power of two >= 1024), is cut into
+// blocks of B nodes, and block k of a region of NA arrays holds B elements of
+// each array in turn: element (a, n) at (n / B) NA B + a B + n % B.  B is 32
+// KiB of population storage (8192 nodes in FP32, 16384 in 16-bit, 4096 in
+// FP64), or the next power of two >= N for a smaller domain.  Every block
+// starts 256-byte aligned and the moments sweep needs no tail.
 // lb_init and lb_moments stage their host transfers through m, which the
 // next step's moments sweep rewrites anyway; the library allocates nothing
 // beyond lb_required_bytes on the device.
@@ -39,7 +44,6 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
 }
 
 
-constexpr int64_t kPadNodes = 4096;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -115,7 +119,11 @@ Layout layout_of(const lb_params* p) {
   L.ssize = p->storage == LB_STORE_F64 ? 8 : p->storage == LB_STORE_F32 ? 4 : 2;
   L.csize = p->compute == LB_COMPUTE_F64 ? 8 : 4;
   L.N = p->nx * p->ny * p->nz;
-  L.npad = (L.N + kPadNodes - 1) / kPadNodes * kPadNodes;
+  int lb = 10;  // block of B = 2^lb nodes: 32 KiB of populations, >= 1024 nodes
+  while ((int64_t(1) << lb) < L.N && (int64_t(1) << lb) * (int64_t)L.ssize < 32768) ++lb;
+  L.lb = lb;
+  const int64_t B = int64_t(1) << lb;
+  L.npad = (L.N + B - 1) / B * B;
   L.f_off = 0;
   L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
   L.r_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
@@ -151,7 +159,7 @@ void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) 
   q.bbx = p->bc[0] == LB_BOUNCEBACK;
   q.bby = p->bc[1] == LB_BOUNCEBACK;
   q.bbz = p->bc[2] == LB_BOUNCEBACK;
-  q.pad_ = 0;
+  q.lb = L.lb;
   q.rho0 = (C)p->rho0;
   q.inv_rho0 = (C)(1.0 / p->rho0);
   for (int a = 0; a < 3; ++a) {
@@ -325,11 +333,12 @@ int lb_sweep(lb_handle* h, int which) {
 }
 
 int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
-              int64_t* array_stride) {
-  if (!h || !pop_offset || !moment_offset || !array_stride) return LB_EINVAL;
+              int64_t* block_nodes, int64_t* padded_nodes) {
+  if (!h || !pop_offset || !moment_offset || !block_nodes || !padded_nodes) return LB_EINVAL;
   *pop_offset = h->L.f_off;
   *moment_offset = h->L.m_off;
-  *array_stride = h->L.npad;
+  *block_nodes = int64_t(1) << h->L.lb;
+  *padded_nodes = h->L.npad;
   return LB_OK;
 }
 

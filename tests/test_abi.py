@@ -115,3 +115,33 @@ def test_strerror_and_null_destroy():
     assert lb.load().lb_step(None, 1) == lb.LB_EINVAL
     assert lb.load().lb_moments(None, None, None, None, None, None) == lb.LB_EINVAL
     assert lb.load().lb_copy(None, None, 16, None) == lb.LB_EINVAL
+
+
+def _blocked_bytes(Q, M, N, ssize, csize, species=1):
+    """Footprint of the documented blocked layout: block B = 32 KiB of
+    population storage (at least 1024 nodes, at most the next power of two
+    >= N), node count padded to a multiple of B, each region 256-byte
+    aligned, plus 64 KiB of FP64 reduction partials."""
+    B = 1024
+    while B < N and B * ssize < 32768:
+        B *= 2
+    npad = -(-N // B) * B
+    al = lambda v: -(-v // 256) * 256
+    return al(species * Q * npad * ssize) + al(M * npad * csize) + al(1024 * 8 * 8), B, npad
+
+
+def test_required_bytes_of_ragged_domains():
+    cases = [
+        (dict(lattice=19, nx=37, ny=5, nz=7), 19, 10, 4, 4, 1),
+        (dict(lattice=19, nx=100, ny=90, nz=3), 19, 10, 4, 4, 1),
+        (dict(lattice=9, nx=300, ny=70, nz=1, storage=lb.LB_STORE_F16S), 9, 6, 2, 4, 1),
+        (dict(lattice=27, nx=20, ny=19, nz=18, hermite_order=3, storage=lb.LB_STORE_F64,
+              compute=lb.LB_COMPUTE_F64), 27, 10, 8, 8, 1),
+        (dict(lattice=19, nx=24, ny=20, nz=18, species=2, sigma=0.03, beta=0.7), 19, 11, 4, 4, 2),
+        (dict(lattice=19, nx=1, ny=1, nz=1), 19, 10, 4, 4, 1),
+    ]
+    for kw, Q, M, ss, cs, sp in cases:
+        p = lb.lb_params_default(**kw)
+        N = p.nx * p.ny * p.nz
+        want, B, npad = _blocked_bytes(Q, M, N, ss, cs, sp)
+        assert lb.lb_required_bytes(p) == want, (kw, B, npad)

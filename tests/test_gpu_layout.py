@@ -1,0 +1,87 @@
+"""The device layout that lb_layout documents (blocked structure of arrays).
+
+The raw population region, decoded with the documented formula
+(element (a, n) of a region of NA arrays at (n // B) NA B + a B + n % B),
+must hold at every node the oracle's equilibrium populations of the
+initial fields (stored shifted, f_a - t_a rho0); the population ordering is
+internal, so each node's values are compared as a multiset.  The moment
+region after the moments sweep must hold drho and j of every node.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_06437_amd import inputs, lb
+from paper_2304_06437_amd.sim import Simulation, make_params
+
+pytestmark = pytest.mark.gpu
+
+NP = {"f32": np.float32, "f16s": np.float16, "f64": np.float64}
+# (lattice, shape, storage, species): one block, several blocks with a
+# ragged tail, 16-bit blocks, FP64 blocks, and the two-species 2Q region
+CASES = [
+    (19, (37, 5, 7), "f32", 1),
+    (19, (100, 90, 3), "f32", 1),
+    (9, (300, 70, 1), "f16s", 1),
+    (27, (20, 19, 18), "f64", 1),
+    (19, (24, 20, 18), "f32", 2),
+]
+
+
+def _decode(region, NA, B, N):
+    n = np.arange(N)
+    idx = (n // B)[None, :] * (NA * B) + np.arange(NA)[:, None] * B + (n % B)[None, :]
+    return region[idx]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_population_layout_matches_documentation(case):
+    lattice, shape, storage, species = CASES[case]
+    kw = dict(sigma=0.03, beta=0.7) if species == 2 else {}
+    p = make_params(lattice=lattice, shape=shape, storage=storage, species=species, **kw)
+    sim = Simulation(p)
+    N, D = sim.N, sim.D
+    rho, u = inputs.random_state(N, D, seed=case, drho=1e-2, du=0.05)
+    phi = np.where(np.random.default_rng(case).uniform(size=N) > 0.5, 1.0, -1.0) if species == 2 else None
+    sim.init(rho, u, phi)
+    sim.synchronize()
+    pop_off, mom_off, B, npad = lb.lb_layout(sim.handle)
+    assert B & (B - 1) == 0 and B >= 1024 and npad % B == 0 and npad >= N
+    raw = sim.buffer.cpu().numpy()
+    sim.close()
+
+    c, w, _ = oracle.lattice(lattice)
+    Q = len(w)
+    op = oracle.Params(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2], species=species,
+                       sigma=kw.get("sigma", 0.0), beta=kw.get("beta", 0.0))
+    fe = oracle.init(op, rho, u, phi).reshape(species * Q, N)
+    pops = raw[pop_off:pop_off + species * Q * npad * np.dtype(NP[storage]).itemsize]
+    got = _decode(pops.view(NP[storage]).astype(np.float64), species * Q, B, N)
+    if species == 1:
+        sets = [(got, fe - w[:, None] * 1.0)]
+    else:
+        # set 0: mixture shifted; set 1: red populations
+        sets = [(got[:Q], fe[:Q] + fe[Q:] - w[:, None] * 1.0), (got[Q:], fe[:Q])]
+    tol = {"f32": 2e-7, "f16s": 1e-4, "f64": 1e-14}[storage]
+    for g, ref in sets:
+        err = np.abs(np.sort(g, axis=0) - np.sort(ref, axis=0)).max()
+        assert err <= tol * max(1.0, np.abs(ref).max()), (CASES[case], err)
+
+
+def test_moment_layout_after_moments_sweep():
+    p = make_params(lattice=19, shape=(100, 90, 3), storage="f32")
+    sim = Simulation(p)
+    N = sim.N
+    rho, u = inputs.random_state(N, 3, seed=9, drho=1e-2, du=0.05)
+    sim.init(rho, u)
+    lb.lb_sweep(sim.handle, 0)
+    sim.synchronize()
+    pop_off, mom_off, B, npad = lb.lb_layout(sim.handle)
+    raw = sim.buffer.cpu().numpy()
+    sim.close()
+    M = 10
+    mom = _decode(raw[mom_off:mom_off + M * npad * 4].view(np.float32).astype(np.float64), M, B, N)
+    # drho, then j = rho0 u (no force)
+    assert np.abs(mom[0] - (rho - 1.0)).max() < 1e-7
+    for al in range(3):
+        assert np.abs(mom[1 + al] - u[al]).max() < 1e-7
