@@ -97,7 +97,12 @@ inline void fill_job_desc(const lb_handle* h, void* dst, int64_t start) {
   std::memcpy(dst, &d, sizeof(d));
 }
 
-template <class L, int ORDER, typename S, typename C, int V1, int V2MAX>
+// V1: nodes per lane of the moments sweep.  V2MAX: the widest row
+// vector (nodes per lane) of the stream-collide sweep; a lane's V nodes are
+// H = V/E chunks of E <= EMAX consecutive nodes.  V2MAX and EMAX per lattice
+// and storage type are the fastest measured at 512^3 (D3Q19, D3Q27) and
+// 4096^2 (D2Q9) with the blocked layout.
+template <class L, int ORDER, typename S, typename C, int V1, int V2MAX, int EMAX>
 struct ImplT {
   static hipError_t moments(const lb_handle* h) {
     const auto& p = params_of<C>(h);
@@ -106,11 +111,8 @@ struct ImplT {
                        dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
     return hipGetLastError();
   }
-  // V nodes per lane = H chunks of E nodes; E fills at most 16 bytes of the
-  // wider of the storage and compute types.
   template <int V>
   static hipError_t sc(const lb_handle* h) {
-    constexpr int EMAX = 16 / (int)(sizeof(S) > sizeof(C) ? sizeof(S) : sizeof(C));
     constexpr int E = V < EMAX ? V : EMAX;
     constexpr int HH = V / E;
     const auto& p = params_of<C>(h);
@@ -165,7 +167,6 @@ struct ImplT {
   }
   template <int V>
   static hipError_t bsc(const void* d, int n, int64_t total, hipStream_t s) {
-    constexpr int EMAX = 16 / (int)(sizeof(S) > sizeof(C) ? sizeof(S) : sizeof(C));
     constexpr int E = V < EMAX ? V : EMAX;
     constexpr int HH = V / E;
     hipLaunchKernelGGL((k_stream_collide_batch<L, ORDER, 1, S, C, E, HH>),
@@ -199,13 +200,17 @@ struct ImplT {
 
 template <class L, int ORDER>
 inline const Impl* impl_for_storage(int storage) {
-  constexpr int V2F = (L::Q == 27) ? 4 : 8;
-  constexpr int V2D = (L::Q == 27) ? 2 : 4;
+  constexpr bool Q27 = L::Q == 27;
+  constexpr int V2D = Q27 ? 2 : 4;
+  // FP32: 2 x 2 nodes per lane (4 x 1 for D3Q27); 16-bit storage: one
+  // 16-byte chunk of 8 nodes (4 x 1 for D3Q27)
+  constexpr int V2F = 4, EF = Q27 ? 4 : 2;
+  constexpr int V2H = Q27 ? 4 : 8, EH = Q27 ? 4 : 8;
   switch (storage) {
-    case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, V2D>::get();
-    case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, V2F>::get();
-    case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, V2F>::get();
-    case LB_STORE_BF16S: return ImplT<L, ORDER, __bf16, float, 4, V2F>::get();
+    case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, V2D, 2>::get();
+    case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, V2F, EF>::get();
+    case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, V2H, EH>::get();
+    case LB_STORE_BF16S: return ImplT<L, ORDER, __bf16, float, 4, V2H, EH>::get();
   }
   return nullptr;
 }
