@@ -61,6 +61,7 @@ class _Params(ctypes.Structure):
         ("force", ctypes.c_double * 3),
         ("sigma", ctypes.c_double),
         ("beta", ctypes.c_double),
+        ("wall_u", ctypes.c_double * 18),
     ]
 
 
@@ -79,6 +80,7 @@ class Params:
     species: int = 1
     sigma: float = 0.0
     beta: float = 0.0
+    wall_u: tuple = None         # [axis][low, high][component] wall velocities
 
     @property
     def D(self) -> int:
@@ -101,6 +103,10 @@ class Params:
         p.rho0 = self.rho0
         p.sigma = self.sigma
         p.beta = self.beta
+        if self.wall_u is not None:
+            wu = np.asarray(self.wall_u, dtype=np.float64).reshape(18)
+            for i in range(18):
+                p.wall_u[i] = float(wu[i])
         return p
 
 

@@ -39,6 +39,13 @@
  *        f_a(x + c_a) <- f^pc_a(x), periodic wrap per axis, or halfway
  *        bounce-back f_{abar}(x) <- f^pc_a(x) when x + c_a leaves the
  *        domain across a wall.
+ *   6. moving walls (Section 5, lid-driven cavity, where the lid's motion
+ *        enters through Bouzidi's momentum correction; at the halfway
+ *        position that correction is Ladd's):
+ *        f_{abar}(x) <- f^pc_a(x) - 2 t_a rho0 (c_a . u_w) / cs2,
+ *        with u_w the velocity of the wall that x + c_a crosses; a link that
+ *        leaves across an edge or corner takes the sum over the walls it
+ *        crosses.  rho0 is the wall density of the incompressible model.
  *
  *   Lattices: textbook D2Q9, D3Q19, D3Q27 with cs2 = 1/3 (the paper cites but
  *   does not print the weights).
@@ -72,6 +79,8 @@ typedef struct {
   double force[3];  /* body-force density */
   double sigma;     /* colour-gradient surface tension parameter */
   double beta;      /* recolouring (anti-diffusion) parameter */
+  double wall_u[3][2][3]; /* velocity of the wall at [axis][low, high]: tangential,
+                             bounce-back axes only, one species only */
 } ref_params;
 
 typedef struct {
@@ -250,7 +259,34 @@ static int check_params(const ref_params* p, lattice_t* L) {
   if (!(p->tau > 0.5)) return -1;
   if (p->order != 2 && p->order != 3) return -1;
   if (p->species != 1 && p->species != 2) return -1;
+  /* wall velocities: tangential, on bounce-back axes, one species */
+  for (int al = 0; al < 3; ++al)
+    for (int side = 0; side < 2; ++side)
+      for (int be = 0; be < 3; ++be) {
+        const double v = p->wall_u[al][side][be];
+        if (v == 0.0) continue;
+        if (!p->bb[al] || be == al || be >= L->d || p->species != 1) return -1;
+      }
   return 0;
+}
+
+/* Momentum correction of a link a of node (x, y, z) that leaves the domain
+ * across one or more walls: -2 t_a rho0 (c_a . sum of the crossed walls'
+ * velocities) / cs2. */
+static double wall_term(const lattice_t* L, const ref_params* p, int a, int64_t x, int64_t y,
+                        int64_t z) {
+  const int64_t n[3] = {p->nx, p->ny, p->nz};
+  const int64_t t[3] = {x + L->c[a][0], y + L->c[a][1], z + L->c[a][2]};
+  double cu = 0.0;
+  for (int al = 0; al < 3; ++al) {
+    if (!p->bb[al]) continue;
+    int side = -1;
+    if (t[al] < 0) side = 0;
+    if (t[al] >= n[al]) side = 1;
+    if (side < 0) continue;
+    for (int be = 0; be < 3; ++be) cu += L->c[a][be] * p->wall_u[al][side][be];
+  }
+  return -2.0 * L->w[a] * p->rho0 * cu / CS2;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -394,7 +430,7 @@ static void step_one_species(const lattice_t* L, const ref_params* p, const doub
           if (destination(L, p, a, x, y, z, &t))
             fnew[(int64_t)a * N + t] = fpc[a];
           else
-            fnew[(int64_t)L->opp[a] * N + n] = fpc[a];
+            fnew[(int64_t)L->opp[a] * N + n] = fpc[a] + wall_term(L, p, a, x, y, z);
         }
       }
 }

@@ -96,14 +96,34 @@ def _inside_after_shift(shape_zyx, c, bb, sign):
     return ok
 
 
-def _stream(fpc, c, opp, bb):
-    """Push streaming with periodic wrap and halfway bounce-back."""
+def _wall_gain(shape_zyx, ca, wa, bb, wall_u, rho0):
+    """Population f_a(x) that returns by bounce-back comes from the link
+    -c_a of x itself and gains 2 t_a rho0 (c_a . u_w)/cs2, u_w summed over the
+    walls that x - c_a lies beyond (moving-wall halfway bounce-back)."""
+    nz, ny, nx = shape_zyx
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cu = np.zeros(shape_zyx)
+    for ax, coord, n in ((0, x, nx), (1, y, ny), (2, z, nz)):
+        if not bb[ax]:
+            continue
+        src = coord - ca[ax]
+        for side, beyond in ((0, src < 0), (1, src >= n)):
+            cu += beyond * float(np.dot(ca, wall_u[ax][side]))
+    return 2.0 * wa * rho0 * cu / CS2
+
+
+def _stream(fpc, c, opp, bb, w=None, wall_u=None, rho0=1.0):
+    """Push streaming with periodic wrap and halfway bounce-back (moving walls
+    when wall_u[axis][side] is given)."""
     out = np.empty_like(fpc)
     shape = fpc.shape[1:]
     for a in range(len(c)):
         moved = np.roll(fpc[a], shift=(c[a][2], c[a][1], c[a][0]), axis=(0, 1, 2))
         has_source = _inside_after_shift(shape, c[a], bb, -1)
-        out[a] = np.where(has_source, moved, fpc[opp[a]])
+        back = fpc[opp[a]]
+        if wall_u is not None:
+            back = back + _wall_gain(shape, c[a].astype(np.float64), w[a], bb, wall_u, rho0)
+        out[a] = np.where(has_source, moved, back)
     return out
 
 
@@ -152,11 +172,13 @@ def simulate(p, rho, u, nsteps, phi=None):
             out = out + wq * p.rho0 * np.einsum("qabc,abc...->q...", H3, uuu) / (6 * CS2**3)
         return out
 
+    wu = None if p.wall_u is None else np.asarray(p.wall_u, dtype=np.float64).reshape(3, 2, 3)
     f0 = feq_of(rho, u)
     if p.species == 1:
         f = f0
         for _ in range(nsteps):
-            f = _stream(_collide(f, c, w, D, p.tau, p.rho0, F, p.order), c, opp, p.bb)
+            f = _stream(_collide(f, c, w, D, p.tau, p.rho0, F, p.order), c, opp, p.bb, w, wu,
+                        p.rho0)
         g = f
         ph = None
     else:
