@@ -83,6 +83,8 @@ def cpu_baseline(workload: str = "d3q19_tg", seconds_hint: float = 15.0):
               order=w["order"], species=w["species"])
     if w["flow"] == "channel":
         kw.update(force=(1e-6, 0.0, 0.0), bb=(0, 0, 1))
+    if w["flow"] == "cavity":
+        kw.update(bb=(1, 1, 0), wall_u=lid_walls())
     if w["species"] == 2:
         kw.update(sigma=0.03, beta=0.7)
     p = oracle.Params(**kw)
@@ -176,7 +178,19 @@ WORKLOADS = {
                              "beta 0.7"),
     "d2q9_tg": dict(lattice=9, n=4096, tau=0.8, flow="tg2d", order=2, species=1,
                     desc="D2Q9 {n}^2 periodic 2D Taylor-Green (u0 0.01, tau 0.8)"),
+    "d2q9_cavity": dict(lattice=9, n=4096, tau=0.6, flow="cavity", order=2, species=1,
+                        desc="D2Q9 {n}^2 lid-driven cavity: bounce-back walls on all four "
+                             "sides, lid (high y) moving along x at 0.05, tau 0.6, fluid at rest"),
 }
+
+LID = 0.05
+
+
+def lid_walls():
+    """wall velocity [axis][low, high][component] of the cavity lid."""
+    wu = [[[0.0] * 3 for _ in range(2)] for _ in range(3)]
+    wu[1][1][0] = LID
+    return wu
 
 
 def workload_fields(w, n):
@@ -191,6 +205,10 @@ def workload_fields(w, n):
     if w["flow"] == "droplets":
         centres = inputs.droplet_centres(n, 64, 12.0, gap=2.0, seed=7)
         return inputs.droplets(n, centres, 12.0)
+    if w["flow"] == "cavity":
+        D = 2 if w["lattice"] == 9 else 3
+        N = n * n * (1 if D == 2 else n)
+        return np.ones(N), np.zeros((D, N)), None
     raise ValueError(w["flow"])
 
 
@@ -228,6 +246,8 @@ def main():
               storage=args.storage, species=w["species"])
     if w["flow"] == "channel":
         kw.update(force=(1e-6, 0.0, 0.0), bc=(0, 0, 1))
+    if w["flow"] == "cavity":
+        kw.update(bc=(1, 1, 0), wall_velocity=lid_walls())
     if w["species"] == 2:
         kw.update(sigma=0.03, beta=0.7)
     params = make_params(**kw)

@@ -93,6 +93,20 @@ typedef struct lb_params {
   double beta;            /* recolouring parameter (species = 2), 0..1 */
   int32_t storage;        /* enum lb_storage */
   int32_t compute;        /* enum lb_compute */
+  double wall_velocity[3][2][3];
+                          /* velocity of the wall on the low ([a][0]) and high
+                             ([a][1]) face of axis a (Section 5, lid-driven
+                             cavity: the lid's motion enters through Bouzidi's
+                             momentum correction, which at the halfway wall
+                             is Ladd's): a link a leaving node x across a
+                             wall comes back as
+                               f_abar(x) = f^pc_a(x) - 2 t_a rho0 (c_a.u_w)/cs2,
+                             summed over every wall it crosses (edges and
+                             corners).  Only tangential components on
+                             bounce-back axes, one species: LB_EINVAL for a
+                             non-zero normal component or a velocity on a
+                             periodic axis, LB_EUNSUPPORTED with two species.
+                             Zero (the default) = resting walls. */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

@@ -50,6 +50,12 @@ struct StepParams {
   C halfF[3];
   C omw;               // 1 - omega
   C omhw;              // 1 - omega/2
+  // Moving walls: wall[2 axis + side] = -6 rho0 u_w / wden of the wall on
+  // the low (side 0) or high (side 1) face of an axis; moving != 0 if any
+  // is non-zero.
+  int32_t moving;
+  int32_t pad2_;
+  C wall[6][3];
 };
 
 // -------------------------------------------------------------------------
@@ -213,9 +219,10 @@ __device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
   }
 }
 
-// Shifted post-collision value of link a from prescaled coefficients.
+// Shifted post-collision value of link a from prescaled coefficients:
+// wmul_a times a signed sum of coefficients (link_sum).
 template <class L, int ORDER, int A, typename C>
-__device__ __forceinline__ C link_value(const C (&k)[CoefLayout<L, ORDER>::K]) {
+__device__ __forceinline__ C link_sum(const C (&k)[CoefLayout<L, ORDER>::K]) {
   using CL = CoefLayout<L, ORDER>;
   constexpr int D = L::D;
   constexpr int c0 = L::c[A][0], c1 = L::c[A][1], c2 = L::c[A][2];
@@ -248,9 +255,38 @@ __device__ __forceinline__ C link_value(const C (&k)[CoefLayout<L, ORDER>::K]) {
     if (c0 * c1 * c2 > 0) v += k[CL::T + 6];
     if (c0 * c1 * c2 < 0) v -= k[CL::T + 6];
   }
+  return v;
+}
+
+template <class L, int ORDER, int A, typename C>
+__device__ __forceinline__ C link_value(const C (&k)[CoefLayout<L, ORDER>::K]) {
   constexpr int mul = L::wmul[A];
+  if constexpr (mul == 1) return link_sum<L, ORDER, A, C>(k);
+  else return C(mul) * link_sum<L, ORDER, A, C>(k);
+}
+
+// Link value plus `extra` in the same prescaled units (wmul_a (sum + extra)).
+template <class L, int ORDER, int A, typename C>
+__device__ __forceinline__ C link_value_plus(const C (&k)[CoefLayout<L, ORDER>::K], C extra) {
+  constexpr int mul = L::wmul[A];
+  const C v = link_sum<L, ORDER, A, C>(k) + extra;
   if constexpr (mul == 1) return v;
   else return C(mul) * v;
+}
+
+// Moving-wall correction of link A leaving across face `face` (2 axis + side),
+// in prescaled units: c_A . wall[face], so that wmul_A times it is
+// -2 t_A rho0 (c_A . u_w)/cs2 (Ladd's momentum correction, which Bouzidi's
+// interpolated bounce-back reduces to at the halfway wall).
+template <class L, int A, typename C>
+__device__ __forceinline__ C wall_dot(const StepParams<C>& p, int face) {
+  C v = C(0);
+#pragma unroll
+  for (int al = 0; al < L::D; ++al) {
+    if (L::c[A][al] > 0) v += p.wall[face][al];
+    if (L::c[A][al] < 0) v -= p.wall[face][al];
+  }
+  return v;
 }
 
 // -------------------------------------------------------------------------
@@ -376,18 +412,38 @@ struct StreamCollide {
         // every node of this row sends link A across a y/z wall: it comes
         // back into the same node as the opposite link
         C bv[E];
+        if (!p.moving) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) bv[e] = link_value<L, ORDER, A, C>(own[h][e]);
+          for (int e = 0; e < E; ++e) bv[e] = link_value<L, ORDER, A, C>(own[h][e]);
+        } else {
+          // corrections of every wall the link crosses (edges: the sum)
+          C cw = C(0);
+          if (cy != 0 && (ln.y + cy < 0 || ln.y + cy >= p.ny))
+            cw += wall_dot<L, A, C>(p, 2 + (ln.y + cy < 0 ? 0 : 1));
+          if (cz != 0 && (ln.z + cz < 0 || ln.z + cz >= p.nz))
+            cw += wall_dot<L, A, C>(p, 4 + (ln.z + cz < 0 ? 0 : 1));
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            C extra = cw;
+            if constexpr (cx != 0) {
+              if (p.bbx && cx > 0 && xs + e == p.nx - 1) extra += wall_dot<L, A, C>(p, 1);
+              if (p.bbx && cx < 0 && xs + e == 0) extra += wall_dot<L, A, C>(p, 0);
+            }
+            bv[e] = link_value_plus<L, ORDER, A, C>(own[h][e], extra);
+          }
+        }
         store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
       }
       if constexpr (cx != 0) {
         if (row_in && p.bbx) {
           if (cx > 0 && xs + E == p.nx)
-            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + AB * astride(p)] =
-                Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][E - 1]));
+            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + AB * astride(p)] = Codec<S, C>::store(
+                p.moving ? link_value_plus<L, ORDER, A, C>(own[h][E - 1], wall_dot<L, A, C>(p, 1))
+                         : link_value<L, ORDER, A, C>(own[h][E - 1]));
           if (cx < 0 && xs == 0)
-            f[slot<L::Q>(p, ln.rowbase) + AB * astride(p)] =
-                Codec<S, C>::store(link_value<L, ORDER, A, C>(own[h][0]));
+            f[slot<L::Q>(p, ln.rowbase) + AB * astride(p)] = Codec<S, C>::store(
+                p.moving ? link_value_plus<L, ORDER, A, C>(own[h][0], wall_dot<L, A, C>(p, 0))
+                         : link_value<L, ORDER, A, C>(own[h][0]));
         }
       }
     }

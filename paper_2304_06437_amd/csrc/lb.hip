@@ -104,6 +104,19 @@ int validate(const lb_params* p) {
     default:
       return LB_EINVAL;
   }
+  // moving walls: tangential velocities on bounce-back faces, one species
+  const int D = p->lattice == LB_D2Q9 ? 2 : 3;
+  bool moving = false;
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side)
+      for (int b = 0; b < 3; ++b) {
+        const double v = p->wall_velocity[a][side][b];
+        if (!std::isfinite(v)) return LB_EINVAL;
+        if (v == 0.0) continue;
+        if (p->bc[a] != LB_BOUNCEBACK || b == a || b >= D) return LB_EINVAL;
+        moving = true;
+      }
+  if (moving && p->species == 2) return LB_EUNSUPPORTED;
   // keep every index comfortably inside int64
   const double N = (double)p->nx * (double)p->ny * (double)p->nz;
   if (N > 4.0e12) return LB_EINVAL;
@@ -169,6 +182,17 @@ void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) 
   const double omega = 1.0 / p->tau;
   q.omw = (C)(1.0 - omega);
   q.omhw = (C)(1.0 - 0.5 * omega);
+  // moving walls, prescaled like the momentum coefficient: -6 rho0 u_w / wden
+  const double wden = p->lattice == LB_D3Q27 ? 216.0 : 36.0;
+  q.moving = 0;
+  q.pad2_ = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side)
+      for (int b = 0; b < 3; ++b) {
+        const double v = p->wall_velocity[a][side][b];
+        q.wall[2 * a + side][b] = (C)(-6.0 * p->rho0 * v / wden);
+        if (v != 0.0) q.moving = 1;
+      }
 }
 
 int launch_status(hipError_t e) { return status_of(e); }

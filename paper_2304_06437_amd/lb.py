@@ -45,6 +45,7 @@ class lb_params(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("storage", ctypes.c_int32),
         ("compute", ctypes.c_int32),
+        ("wall_velocity", ctypes.c_double * 18),   # [axis][low, high][component]
     ]
 
 
@@ -127,6 +128,10 @@ def lb_params_default(**overrides) -> lb_params:
         if k in ("bc", "force"):
             for i in range(3):
                 getattr(p, k)[i] = v[i]
+        elif k == "wall_velocity":
+            flat = [float(x) for x in np.asarray(v, dtype=np.float64).reshape(18)]
+            for i in range(18):
+                p.wall_velocity[i] = flat[i]
         else:
             setattr(p, k, v)
     return p

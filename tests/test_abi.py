@@ -2,6 +2,7 @@
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2304_06437_amd import lb
@@ -145,3 +146,26 @@ def test_required_bytes_of_ragged_domains():
         N = p.nx * p.ny * p.nz
         want, B, npad = _blocked_bytes(Q, M, N, ss, cs, sp)
         assert lb.lb_required_bytes(p) == want, (kw, B, npad)
+
+
+def test_wall_velocity_validation():
+    def wv(axis, side, comp, v=0.05):
+        w = np.zeros((3, 2, 3))
+        w[axis, side, comp] = v
+        return w
+    ok = lb.lb_params_default(lattice=9, nx=32, ny=32, nz=1, bc=(1, 1, 0),
+                              wall_velocity=wv(1, 1, 0))
+    assert lb.lb_validate(ok) == lb.LB_OK
+    assert lb.lb_required_bytes(ok) == lb.lb_required_bytes(
+        lb.lb_params_default(lattice=9, nx=32, ny=32, nz=1, bc=(1, 1, 0)))
+    # normal component, periodic axis, z component in 2D, non-finite
+    for bad in (wv(1, 1, 1), wv(0, 0, 1, 0.0) + wv(2, 0, 0), wv(1, 0, 2), wv(1, 1, 0, np.nan)):
+        p = lb.lb_params_default(lattice=9, nx=32, ny=32, nz=1, bc=(1, 1, 0), wall_velocity=bad)
+        assert lb.lb_validate(p) == lb.LB_EINVAL
+    p3 = lb.lb_params_default(lattice=19, bc=(0, 0, 1), wall_velocity=wv(2, 1, 0) + wv(2, 0, 1))
+    assert lb.lb_validate(p3) == lb.LB_OK
+    p3b = lb.lb_params_default(lattice=19, bc=(0, 0, 1), wall_velocity=wv(1, 1, 0))
+    assert lb.lb_validate(p3b) == lb.LB_EINVAL
+    two = lb.lb_params_default(lattice=19, bc=(0, 0, 1), species=2, sigma=0.03, beta=0.7,
+                               wall_velocity=wv(2, 1, 0))
+    assert lb.lb_validate(two) == lb.LB_EUNSUPPORTED
