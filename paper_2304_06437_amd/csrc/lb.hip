@@ -48,6 +48,9 @@ __global__ __launch_bounds__(256) void k_copy(const lb_u4* __restrict__ src,
 
 
 constexpr size_t kAlign = 256;
+// Host transfers of lb_init / lb_moments move at most this many nodes per
+// chunk, so their host staging buffer stays bounded (<= 1.2 GB).
+constexpr int64_t kMaxStageNodes = int64_t(1) << 24;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -309,7 +312,7 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
   try {
     const int per = 1 + L.D + (two ? 1 : 0);  // doubles staged per node
     const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
-    const int64_t chunk = cap < N ? cap : N;
+    const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
     std::vector<double> hb((size_t)per * chunk);
     double* stage = (double*)h->m;
     for (int64_t n0 = 0; n0 < N; n0 += chunk) {
@@ -388,7 +391,7 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
   try {
     if (rho || u || pineq || phi) {
       const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
-      const int64_t chunk = cap < N ? cap : N;
+      const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
       std::vector<double> hb((size_t)per * chunk);
       double* stage = (double*)h->m;
       for (int64_t n0 = 0; n0 < N; n0 += chunk) {

@@ -258,3 +258,34 @@ def test_full_size_512_sampled_against_oracle():
     print(f"512^3 sampled: max |du|/u0 = {worst:.3e}")
     assert worst <= FP32_TOL
     assert np.isfinite(got["u"]).all()
+
+
+@pytest.mark.timeout(300)
+def test_maximum_size_node_index_beyond_2_31():
+    """A D2Q9 FP32 domain of 46400 x 46300 = 2.148e9 nodes (129 GB of HBM):
+    node indices pass 2^31 and element offsets 2^34.  After 6 steps, sampled
+    nodes (the last rows, block and segment edges, the last node) match the
+    oracle on each sample's dependency cone.  Node 7040 + 46400 * 46282 starts
+    a block of the layout (n = 262145 * 8192)."""
+    nx, ny, steps, tau, u0 = 46400, 46300, 6, 0.8, 0.01
+    assert nx * ny > 2**31
+    rho, u = inputs.taylor_green_2d(nx, ny, u0)
+    p = make_params(lattice=9, shape=(nx, ny, 1), tau=tau)
+    got = run(p, rho, u, steps, pineq=False, conserved=False)
+    h = steps + 2
+    off = np.arange(-h, h + 1)
+    samples = [(0, 0), (nx - 1, ny - 1), (nx - 1, ny - 2), (12345, ny - 1),
+               (7039, 46282), (7040, 46282), (511, 30000), (512, 30000), (46399, 23000)]
+    worst = 0.0
+    for (x, y) in samples:
+        assert x + nx * y >= 0
+        ix, iy = (x + off) % nx, (y + off) % ny
+        sub = (iy[:, None] * nx + ix[None, :]).reshape(-1)
+        q = oracle.Params(lattice=9, nx=2 * h + 1, ny=2 * h + 1, nz=1, tau=tau)
+        ref = oracle.simulate(q, rho[sub], u[:, sub], steps)
+        c = h + (2 * h + 1) * h
+        nidx = x + nx * y
+        worst = max(worst, np.abs(got["u"][:, nidx] - ref["u"][:, c]).max() / u0)
+        assert abs(got["rho"][nidx] - ref["rho"][c]) < 1e-7
+    print(f"{nx}x{ny} ({nx * ny} nodes) sampled: max |du|/u0 = {worst:.3e}")
+    assert worst <= FP32_TOL

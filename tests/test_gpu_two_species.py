@@ -1,8 +1,14 @@
 """GPU parity of the two-species colour-gradient step against the oracle.
 
-FP64 storage and arithmetic must reproduce the oracle to rounding; FP32
-errors are measured on phi, rho and u (relative to the largest velocity,
-which here is the spurious current around the interfaces, ~1e-4).
+FP64 storage and arithmetic must reproduce the oracle to rounding.  FP32
+bars come from the rounding sensitivity of the colour-gradient step itself:
+a plain float32 transcription of the same two-array step (numpy, every
+array float32) differs from the FP64 oracle by 1.4e-5 (2D) and 4.8e-5 (3D)
+in max-relative velocity on the droplets-in-a-Taylor-Green-flow cases after
+1000 steps, and by 6.6e-6 to 8.2e-4 on the sharp-start cases (phi = +-1
+steps, random velocities).  The single-species bar (1e-5) is below that
+floor, so droplets in a flow are held to 5e-5 and sharp starts to 1e-4,
+with the errors printed.
 """
 import functools
 
@@ -81,8 +87,44 @@ def test_two_species_fp32_matches_oracle(name):
     e_phi = np.abs(got["phi"] - ref["phi"]).max()
     e_u = max_rel(got["u"], ref["u"])
     e_rho = np.abs(got["rho"] - ref["rho"]).max()
-    print(f"{name} fp32: |dphi| {e_phi:.2e} max-rel u {e_u:.2e} |drho| {e_rho:.2e}")
-    assert e_phi < 1e-4 and e_rho < 1e-5 and e_u < 1e-2
+    e_abs = np.abs(got["u"] - ref["u"]).max()
+    print(f"{name} fp32: |dphi| {e_phi:.2e} max-rel u {e_u:.2e} (max |u| "
+          f"{np.abs(ref['u']).max():.1e}, |du| {e_abs:.2e}) |drho| {e_rho:.2e}")
+    assert e_phi < 1e-4 and e_rho < 1e-5 and e_u <= 1e-4
+
+
+FLOW_CASES = {
+    # name: (lattice, shape, tau, steps, sigma, beta): periodic, Taylor-Green u0 0.02
+    "d3q19_tg_droplets": (19, (48, 32, 32), 0.55, 1000, 0.03, 0.7),
+    "d2q9_tg_droplets": (9, (128, 96, 1), 0.8, 1000, 0.03, 0.7),
+}
+
+
+def _flow_state(lattice, shape):
+    nx, ny, nz = shape
+    _, _, phi = _state(lattice, shape, 5)
+    if lattice == 9:
+        rho, u = inputs.taylor_green_2d(nx, ny, 0.02)
+    else:
+        rho, u = inputs.taylor_green_3d(nx, ny, nz, 0.02)
+    return rho, u, phi
+
+
+@pytest.mark.parametrize("name", sorted(FLOW_CASES))
+def test_two_species_in_a_flow_fp32(name):
+    lattice, shape, tau, steps, sigma, beta = FLOW_CASES[name]
+    rho, u, phi = _flow_state(lattice, shape)
+    q = oracle.Params(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2], tau=tau,
+                      species=2, sigma=sigma, beta=beta)
+    ref = oracle.simulate(q, rho, u, steps, phi=phi)
+    p = make_params(lattice=lattice, shape=shape, tau=tau, storage="f32", species=2,
+                    sigma=sigma, beta=beta)
+    got = run(p, rho, u, steps, phi=phi, phi_out=True)
+    e_u = max_rel(got["u"], ref["u"])
+    e_phi = np.abs(got["phi"] - ref["phi"]).max()
+    print(f"{name} fp32: max-rel u {e_u:.2e} (max |u| {np.abs(ref['u']).max():.1e}), "
+          f"|dphi| {e_phi:.2e}")
+    assert e_u <= 5e-5 and e_phi < 1e-4
 
 
 def test_two_species_conservation():
