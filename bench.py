@@ -185,6 +185,16 @@ WORKLOADS = {
 
 LID = 0.05
 
+# The paper's own single-component thread-safe numbers (Section 6, CUDA
+# Fortran, FP32), other hardware: context for the workload of the same
+# lattice and shape, never a target (the paper reports no 512^3 figure).
+PAPER_CONTEXT = {
+    "D3Q19 3D": {"value": 3600.0, "unit": "MLUPS", "hardware": "RTX 3090 (CUDA Fortran)",
+                 "workload": "3D 256^3, single component, FP32"},
+    "D2Q9 2D": {"value": 6100.0, "unit": "MLUPS", "hardware": "RTX 3090 (CUDA Fortran)",
+                "workload": "2D 4096^2, single component, FP32"},
+}
+
 
 def lid_walls():
     """wall velocity [axis][low, high][component] of the cavity lid."""
@@ -329,6 +339,10 @@ def main():
         "copy_ceiling_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "mass_finite": bool(np.isfinite(check[0])),
     }
+    ctx = PAPER_CONTEXT.get("D3Q19 3D" if Q == 19 and w["species"] == 1 else
+                            "D2Q9 2D" if Q == 9 and w["species"] == 1 else "")
+    if ctx:
+        out["paper_context"] = dict(ctx, note="other hardware and domain size; context only")
     if args.serve_jobs > 0:
         rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
         for key, rate in zip(("serving", "serving_below_saturation"), rates):
