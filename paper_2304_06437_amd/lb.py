@@ -65,6 +65,15 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run paper_2304_06437_amd.build")
+    # PyTorch ships its own HIP runtime.  Loaded first, it is the runtime
+    # liblb.so binds to (same library name), so the streams and device
+    # memory torch hands over belong to the library's runtime; loaded after
+    # liblb.so, a second runtime would come up beside the system one and
+    # torch's streams would be invalid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(lb_params)
     H = ctypes.c_void_p

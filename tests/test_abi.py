@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed: nothing here launches work)."""
 import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -169,3 +170,20 @@ def test_wall_velocity_validation():
     two = lb.lb_params_default(lattice=19, bc=(0, 0, 1), species=2, sigma=0.03, beta=0.7,
                                wall_velocity=wv(2, 1, 0))
     assert lb.lb_validate(two) == lb.LB_EUNSUPPORTED
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not bring up a second HIP
+    runtime (torch's streams would be invalid in it)."""
+    code = (
+        "from paper_2304_06437_amd import lb\n"
+        "lb.load()\n"
+        "import torch\n"
+        "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+        "print(len(maps))\n"
+    )
+    root = os.path.dirname(HERE)
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
