@@ -392,24 +392,29 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
     if (rho || u || pineq || phi) {
       const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
       const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
-      std::vector<double> hb((size_t)per * chunk);
       double* stage = (double*)h->m;
+      // staged rows: rho, u (D), Pi^neq (K), phi; only the requested ones
+      // cross PCIe, straight into the caller's arrays
+      auto fetch = [&](double* dst, int row, int64_t cnt) -> hipError_t {
+        return hipMemcpyAsync(dst, stage + (size_t)row * cnt, cnt * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream);
+      };
       for (int64_t n0 = 0; n0 < N; n0 += chunk) {
         const int64_t cnt = (N - n0 < chunk) ? N - n0 : chunk;
-        LB_TRY_HIP(h->impl->readout(h, stage, n0, cnt));
-        LB_TRY_HIP(hipMemcpyAsync(hb.data(), stage, (size_t)per * cnt * sizeof(double),
-                                  hipMemcpyDeviceToHost, h->stream));
-        LB_TRY_HIP(hipStreamSynchronize(h->stream));
-        if (rho) std::memcpy(rho + n0, hb.data(), cnt * sizeof(double));
-        if (u)
-          for (int al = 0; al < L.D; ++al)
-            std::memcpy(u + (size_t)al * N + n0, &hb[(size_t)(1 + al) * cnt], cnt * sizeof(double));
-        if (pineq)
-          for (int q = 0; q < K; ++q)
-            std::memcpy(pineq + (size_t)q * N + n0, &hb[(size_t)(1 + L.D + q) * cnt],
-                        cnt * sizeof(double));
-        if (phi)
-          std::memcpy(phi + n0, &hb[(size_t)(1 + L.D + K) * cnt], cnt * sizeof(double));
+        // keep the first error, but always drain the stream before returning:
+        // no copy into the caller's arrays may still be in flight afterwards
+        hipError_t err = h->impl->readout(h, stage, n0, cnt);
+        auto keep = [&](hipError_t e) { if (err == hipSuccess) err = e; };
+        if (err == hipSuccess) {
+          if (rho) keep(fetch(rho + n0, 0, cnt));
+          if (u)
+            for (int al = 0; al < L.D; ++al) keep(fetch(u + (size_t)al * N + n0, 1 + al, cnt));
+          if (pineq)
+            for (int q = 0; q < K; ++q) keep(fetch(pineq + (size_t)q * N + n0, 1 + L.D + q, cnt));
+          if (phi) keep(fetch(phi + n0, 1 + L.D + K, cnt));
+        }
+        keep(hipStreamSynchronize(h->stream));
+        if (err != hipSuccess) return status_of(err);
       }
     }
     int st = LB_OK;

@@ -71,7 +71,8 @@ def taylor_green_3d(nx: int, ny: int, nz: int, u0: float, rho0: float = 1.0):
 
     u = u0 sin kx cos ky cos kz, v = -u0 cos kx sin ky cos kz, w = 0,
     rho = rho0 + (3 u0^2 / 16)(cos 2kx + cos 2ky)(cos 2kz + 2).
-    Built from 1D factors broadcast over the grid.
+    Divergence-free for nx = ny (kx = ky); on other boxes it is a smooth
+    periodic test field.  Built from 1D factors broadcast over the grid.
     """
     kx, ky, kz = 2 * math.pi / nx, 2 * math.pi / ny, 2 * math.pi / nz
     x = _axis(nx)[None, None, :]
@@ -152,3 +153,18 @@ def random_state(N: int, D: int, seed: int, drho: float = 1e-2, du: float = 0.05
     """Uniform random density and velocity fields (for small consistency tests)."""
     rng = np.random.default_rng(seed)
     return rho0 + drho * rng.uniform(-1, 1, N), du * rng.uniform(-1, 1, (D, N))
+
+
+def ellipsoid_droplet(n: int, radii, centre=None, rho0: float = 1.0):
+    """phi = +1 inside the ellipsoid (x/a)^2 + (y/b)^2 + (z/c)^2 <= 1 around
+    `centre` (default: the middle of the periodic cube of side n), -1
+    outside; fluid at rest.  An oblate droplet of equivalent radius R and
+    deformation d has radii (R(1+d), R(1+d), R/(1+d)^2)."""
+    c = np.full(3, (n - 1) / 2.0) if centre is None else np.asarray(centre, dtype=np.float64)
+    a, b, cz = radii
+    z = np.arange(n, dtype=np.float64)[:, None, None]
+    y = np.arange(n, dtype=np.float64)[None, :, None]
+    x = np.arange(n, dtype=np.float64)[None, None, :]
+    inside = ((x - c[0]) / a) ** 2 + ((y - c[1]) / b) ** 2 + ((z - c[2]) / cz) ** 2 <= 1.0
+    N = n ** 3
+    return np.full(N, rho0), np.zeros((3, N)), np.where(inside, 1.0, -1.0).reshape(-1)
