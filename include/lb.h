@@ -116,10 +116,11 @@ typedef struct lb_handle lb_handle;
 void lb_params_default(lb_params* p);
 
 /* Exact number of device bytes lb_create needs for these parameters:
- * populations (species * Q arrays) + moments (M arrays) + reduction scratch,
- * each array padded to a 256-byte boundary (Section 4 counts 15 arrays for
- * D2Q9 and 29 for D3Q19 in single precision).  Returns 0 for invalid
- * parameters. */
+ * populations (species * Q arrays) + moments (M arrays) of npad nodes each,
+ * npad = N rounded up to the layout's block size (see lb_layout), each
+ * region 256-byte aligned, + 64 KiB of FP64 reduction scratch (Section 4
+ * counts 15 arrays per node for D2Q9 and 29 for D3Q19 in single precision).
+ * Returns 0 for invalid parameters. */
 size_t lb_required_bytes(const lb_params* p);
 
 /* Validate parameters without touching the device. */
