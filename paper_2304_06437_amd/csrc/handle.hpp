@@ -101,9 +101,12 @@ inline void fill_job_desc(const lb_handle* h, void* dst, int64_t start) {
 // vector (nodes per lane) of the stream-collide sweep; a lane's V nodes are
 // H = V/E chunks of E <= EMAX consecutive nodes.  V2MAX and EMAX per lattice
 // and storage type are the fastest measured at 512^3 (D3Q19, D3Q27) and
-// 4096^2 (D2Q9) with the blocked layout.
+// 4096^2 (D2Q9) with the blocked layout.  FD: the short division of the
+// coefficient prescaling (see scaled), for the instruction-bound D3Q27
+// 16-bit sweeps.
 template <class L, int ORDER, typename S, typename C, int V1, int V2MAX, int EMAX>
 struct ImplT {
+  static constexpr bool FD = L::Q == 27 && sizeof(S) == 2;
   static hipError_t moments(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     const int64_t threads = p.npad / V1;
@@ -117,7 +120,7 @@ struct ImplT {
     constexpr int HH = V / E;
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH>),
+    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH, FD>),
                        dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, h->stream,
                        (const C*)h->m, (S*)h->f, p);
     return hipGetLastError();
@@ -169,7 +172,7 @@ struct ImplT {
   static hipError_t bsc(const void* d, int n, int64_t total, hipStream_t s) {
     constexpr int E = V < EMAX ? V : EMAX;
     constexpr int HH = V / E;
-    hipLaunchKernelGGL((k_stream_collide_batch<L, ORDER, 1, S, C, E, HH>),
+    hipLaunchKernelGGL((k_stream_collide_batch<L, ORDER, 1, S, C, E, HH, FD>),
                        dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const JobDesc<C>*)d,
                        n, total);
     return hipGetLastError();

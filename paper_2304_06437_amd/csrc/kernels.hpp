@@ -131,18 +131,21 @@ __device__ __forceinline__ void node_moments(const C (&s)[L::Q], const StepParam
   }
 }
 
-// x * NUM / DEN with one rounding's worth of error and no bias: the odd part
-// of the reduced denominator is a division, the power-of-two part an exact
-// scaling.  The division by the odd integer d is a multiplication by the
-// rounded reciprocal r followed by one Newton correction with the exact
-// residual, q' = q + (x - q d) r: the result is within an ulp of x / d and
-// its error has no fixed sign.  (A plain multiplication by r carries r's
-// rounding error, the same relative error with the same sign at every
-// node and step, which would accumulate as a drift of the conserved
-// momentum.)  Three instructions instead of a full IEEE division.
+// x * NUM / DEN with no bias: the odd part d of the reduced denominator is a
+// division, the power-of-two part an exact scaling.  (A multiplication by
+// the rounded reciprocal r = fl(1/d) alone carries r's rounding error, the
+// same relative error with the same sign at every node and step, which
+// accumulates as a drift of the conserved momentum.)  Two ways to divide:
+//   FD = false: IEEE division, correctly rounded;
+//   FD = true:  q = x r, then one Newton correction with the exact FMA
+//               residual, q' = q + (x - q d) r: within an ulp of x / d, no
+//               fixed sign, three instructions instead of about ten.
+// The stream-collide sweeps bound by instruction issue (D3Q27 third order
+// with 16-bit storage) use FD = true; the bandwidth-bound ones measure
+// faster with the IEEE sequence.
 __host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
-template <int NUM, int DEN, typename C>
+template <int NUM, int DEN, bool FD = false, typename C>
 __device__ __forceinline__ C scaled(C x) {
   constexpr int g = gcd_int(NUM, DEN);
   constexpr int n = NUM / g, d = DEN / g;
@@ -152,10 +155,14 @@ __device__ __forceinline__ C scaled(C x) {
   C y = x;
   if constexpr (n != 1) y = y * C(n);
   if constexpr (dodd != 1) {
-    constexpr C r = C(1) / C(dodd);
-    const C q = y * r;
-    const C e = fma(-q, C(dodd), y);  // exact: q is within an ulp of y / d
-    y = fma(e, r, q);
+    if constexpr (FD) {
+      constexpr C r = C(1) / C(dodd);
+      const C q = y * r;
+      const C e = fma(-q, C(dodd), y);  // exact: q is within an ulp of y / d
+      y = fma(e, r, q);
+    } else {
+      y = y / C(dodd);
+    }
   }
   if constexpr (d2 != 1) y = y * C(1.0 / d2);
   return y;
@@ -171,7 +178,7 @@ __device__ __forceinline__ C scaled(C x) {
 // Hermite form.  The coefficients are prescaled (CoefLayout) so that a link
 // value is a signed sum times a power of two, computed once per node instead
 // of once per link.
-template <class L, int ORDER, typename C>
+template <class L, int ORDER, typename C, bool FD = false>
 __device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
                                                const StepParams<C>& p,
                                                C (&k)[CoefLayout<L, ORDER>::K]) {
@@ -190,18 +197,18 @@ __device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
   for (int al = 0; al < D; ++al) {
     const C A = p.rho0 * u[al] * u[al] + p.omw * m[ML::PID + al] + p.omhw * C(2) * u[al] * p.F[al];
     trA += A;
-    k[CL::AD + al] = scaled<9, 2 * W>(A);   // 4.5 A / wden
+    k[CL::AD + al] = scaled<9, 2 * W, FD>(A);   // 4.5 A / wden
 #pragma unroll
     for (int be = al + 1; be < D; ++be) {
       const int o = offdiag(al, be);
       const C Ao = p.rho0 * u[al] * u[be] + p.omw * m[ML::PIO + o] +
                    p.omhw * (u[al] * p.F[be] + p.F[al] * u[be]);
-      k[CL::AO + o] = scaled<9, W>(Ao);
+      k[CL::AO + o] = scaled<9, W, FD>(Ao);
     }
   }
-  k[CL::R] = scaled<1, W>(m[ML::RHO] - C(1.5) * trA);
+  k[CL::R] = scaled<1, W, FD>(m[ML::RHO] - C(1.5) * trA);
 #pragma unroll
-  for (int be = 0; be < D; ++be) k[CL::J + be] = scaled<3, W>(Jt[be]);
+  for (int be = 0; be < D; ++be) k[CL::J + be] = scaled<3, W, FD>(Jt[be]);
   if constexpr (ORDER >= 3) {
     static_assert(L::Q == 27, "third-order terms need D3Q27");
     C B[3][3];
@@ -221,26 +228,30 @@ __device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
       for (int be = 0; be < 3; ++be) {
         if (be == al) continue;
         const C a3 = p.rho0 * u[al] * u[al] * u[be] + C(2) * u[al] * B[al][be] + u[be] * B[al][al];
-        k[CL::T + t3slot(al, be)] = scaled<27, 2 * W>(a3);  // 13.5 a3 / wden
+        k[CL::T + t3slot(al, be)] = scaled<27, 2 * W, FD>(a3);  // 13.5 a3 / wden
         sum3[be] += a3;
       }
 #pragma unroll
-    for (int be = 0; be < 3; ++be) k[CL::J + be] -= scaled<9, 2 * W>(sum3[be]);
+    for (int be = 0; be < 3; ++be) k[CL::J + be] -= scaled<9, 2 * W, FD>(sum3[be]);
     const C axyz = p.rho0 * u[0] * u[1] * u[2] + u[0] * B[1][2] + u[1] * B[0][2] + u[2] * B[0][1];
-    k[CL::T + 6] = scaled<27, W>(axyz);
+    k[CL::T + 6] = scaled<27, W, FD>(axyz);
   }
 }
 
 // Shifted post-collision value of link a from prescaled coefficients:
-// wmul_a times a signed sum of coefficients.  The sum splits into an even
-// part (orders 0 and 2: the same for c_a and -c_a) and an odd part (orders 1
-// and 3: opposite signs), so a pair of opposite links costs one of each.
+// wmul_a times a signed sum of coefficients (link_sum).
 template <class L, int ORDER, int A, typename C>
-__device__ __forceinline__ C link_even(const C (&k)[CoefLayout<L, ORDER>::K]) {
+__device__ __forceinline__ C link_sum(const C (&k)[CoefLayout<L, ORDER>::K]) {
   using CL = CoefLayout<L, ORDER>;
   constexpr int D = L::D;
-  constexpr int cv[3] = {L::c[A][0], L::c[A][1], L::c[A][2]};
+  constexpr int c0 = L::c[A][0], c1 = L::c[A][1], c2 = L::c[A][2];
+  constexpr int cv[3] = {c0, c1, c2};
   C v = k[CL::R];
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    if (cv[al] > 0) v += k[CL::J + al];
+    if (cv[al] < 0) v -= k[CL::J + al];
+  }
 #pragma unroll
   for (int al = 0; al < D; ++al)
     if (cv[al] != 0) v += k[CL::AD + al];
@@ -251,24 +262,6 @@ __device__ __forceinline__ C link_even(const C (&k)[CoefLayout<L, ORDER>::K]) {
       if (cv[al] * cv[be] > 0) v += k[CL::AO + offdiag(al, be)];
       if (cv[al] * cv[be] < 0) v -= k[CL::AO + offdiag(al, be)];
     }
-  return v;
-}
-
-// Odd part of link A (A not the rest link).
-template <class L, int ORDER, int A, typename C>
-__device__ __forceinline__ C link_odd(const C (&k)[CoefLayout<L, ORDER>::K]) {
-  using CL = CoefLayout<L, ORDER>;
-  constexpr int D = L::D;
-  constexpr int c0 = L::c[A][0], c1 = L::c[A][1], c2 = L::c[A][2];
-  constexpr int cv[3] = {c0, c1, c2};
-  constexpr int a0 = c0 != 0 ? 0 : (c1 != 0 ? 1 : 2);  // first moving axis
-  static_assert(cv[a0] != 0, "link_odd: the rest link has no odd part");
-  C v = cv[a0] > 0 ? k[CL::J + a0] : -k[CL::J + a0];
-#pragma unroll
-  for (int al = a0 + 1; al < D; ++al) {
-    if (cv[al] > 0) v += k[CL::J + al];
-    if (cv[al] < 0) v -= k[CL::J + al];
-  }
   if constexpr (ORDER >= 3) {
 #pragma unroll
     for (int al = 0; al < 3; ++al)
@@ -285,18 +278,19 @@ __device__ __forceinline__ C link_odd(const C (&k)[CoefLayout<L, ORDER>::K]) {
 }
 
 template <class L, int ORDER, int A, typename C>
-__device__ __forceinline__ C link_sum(const C (&k)[CoefLayout<L, ORDER>::K]) {
-  if constexpr (L::c[A][0] == 0 && L::c[A][1] == 0 && L::c[A][2] == 0)
-    return link_even<L, ORDER, A, C>(k);
-  else
-    return link_even<L, ORDER, A, C>(k) + link_odd<L, ORDER, A, C>(k);
-}
-
-template <class L, int ORDER, int A, typename C>
 __device__ __forceinline__ C link_value(const C (&k)[CoefLayout<L, ORDER>::K]) {
   constexpr int mul = L::wmul[A];
   if constexpr (mul == 1) return link_sum<L, ORDER, A, C>(k);
   else return C(mul) * link_sum<L, ORDER, A, C>(k);
+}
+
+// Link value plus `extra` in the same prescaled units (wmul_a (sum + extra)).
+template <class L, int ORDER, int A, typename C>
+__device__ __forceinline__ C link_value_plus(const C (&k)[CoefLayout<L, ORDER>::K], C extra) {
+  constexpr int mul = L::wmul[A];
+  const C v = link_sum<L, ORDER, A, C>(k) + extra;
+  if constexpr (mul == 1) return v;
+  else return C(mul) * v;
 }
 
 // Moving-wall correction of link A leaving across face `face` (2 axis + side),
@@ -363,17 +357,10 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 // Lane mapping: a wavefront's segment of 64 V nodes (V = E H) is split into H
 // chunks of 64 E nodes; lane l owns nodes h*64E + l*E + e (e < E) of chunk h.
 // Every vector load or store instruction therefore covers 64 E contiguous
-// nodes: whole cache lines per instruction.
-//
-// Link values are computed where they start (push form): for every node of
-// the lane, the links c_a and -c_a come as a pair from one even and one odd
-// signed sum (link_even, link_odd).  The x part of the streaming then moves
-// the finished values by one node inside the lane or across lanes (one
-// shuffle per x-moving link), the y and z parts are stores into the rows
-// (y + c_ay, z + c_az).  The two nodes just outside the segment are the only
-// ones whose coefficients a wavefront evaluates besides its own.
+// nodes (16 bytes per lane for E = 4 floats): whole cache lines per
+// instruction.
 // -------------------------------------------------------------------------
-template <class L, int ORDER, typename S, typename C, int E, int H>
+template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
 struct StreamCollide {
   using ML = MomentLayout<L>;
   using CL = CoefLayout<L, ORDER>;
@@ -384,20 +371,16 @@ struct StreamCollide {
   struct Lane {
     int64_t xh[H];    // first node of this lane's chunk h
     bool act[H];      // chunk h inside the row
-    int64_t y, z, rowbase, xend;
-    int lane;
+    int64_t y, z, rowbase;
   };
 
-  // Stream the values v (link X, evaluated at this lane's nodes as sources)
-  // to their destinations; hv[X] is link X of the node just left (c_x > 0;
-  // valid in lane 0) or right (c_x < 0; valid in the lane holding the
-  // segment's last node) of the segment.
-  template <int X>
-  __device__ __forceinline__ static void emit(S* __restrict__ f, const StepParams<C>& p,
-                                              const C (&v)[H][E], const C (&hv)[L::Q],
-                                              const Lane& ln) {
-    constexpr int cx = L::c[X][0], cy = L::c[X][1], cz = L::c[X][2];
-    constexpr int XB = opposite<L>(X);
+  // Emit link A for this lane's nodes.
+  template <int A>
+  __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
+                                              const C (&own)[H][E][K], const C (&left)[H][K],
+                                              const C (&right)[H][K], const Lane& ln) {
+    constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
+    constexpr int AB = opposite<L>(A);
     int64_t ty = ln.y + cy, tz = ln.z + cz;
     bool row_in = true;
     if (cy != 0) {
@@ -412,149 +395,86 @@ struct StreamCollide {
         else tz = (tz < 0) ? p.nz - 1 : 0;
       }
     }
-    if (row_in) {
-      // values arriving at this lane's nodes from x - cx
-      C in[H][E];
-      if constexpr (cx == 0) {
+    const int64_t trow = p.nx * (ty + p.ny * tz);
 #pragma unroll
-        for (int h = 0; h < H; ++h)
+    for (int h = 0; h < H; ++h) {
+      if (!ln.act[h]) continue;
+      const int64_t xs = ln.xh[h];
+      if (row_in) {
+        // value arriving at x (this lane's nodes) from source x - cx of this row
+        C val[E];
 #pragma unroll
-          for (int e = 0; e < E; ++e) in[h][e] = v[h][e];
-      } else if constexpr (cx > 0) {
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-#pragma unroll
-          for (int e = 1; e < E; ++e) in[h][e] = v[h][e - 1];
-          in[h][0] = lane_from_below(v[h][E - 1]);
-          if (h > 0) {
-            const C t = lane_bcast(v[h - 1][E - 1], 63);
-            if (ln.lane == 0) in[h][0] = t;
+        for (int e = 0; e < E; ++e) {
+          if constexpr (cx == 0) {
+            val[e] = link_value<L, ORDER, A, C>(own[h][e]);
+          } else if constexpr (cx > 0) {
+            val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[h][e > 0 ? e - 1 : 0])
+                             : link_value<L, ORDER, A, C>(left[h]);
+          } else {
+            val[e] = (e < E - 1) ? link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0])
+                                 : link_value<L, ORDER, A, C>(right[h]);
           }
         }
-        if (ln.lane == 0) in[0][0] = hv[X];
-      } else {
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-#pragma unroll
-          for (int e = 0; e < E - 1; ++e) in[h][e] = v[h][e + 1];
-          in[h][E - 1] = lane_from_above(v[h][0]);
-          if (h < H - 1) {
-            const C t = lane_bcast(v[h + 1][0], 0);
-            if (ln.lane == 63) in[h][E - 1] = t;
-          }
-        }
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-          if (ln.act[h] && ln.xh[h] + E == ln.xend) in[h][E - 1] = hv[X];
-      }
-      const int64_t trow = p.nx * (ty + p.ny * tz);
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (!ln.act[h]) continue;
-        const int64_t xs = ln.xh[h];
-        S* dst = f + slot<L::Q>(p, trow + xs) + X * astride(p);
+        S* dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
         const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
         const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);    // source x = nx
         if (!(cut_lo || cut_hi)) {
-          store_pack<S, C, E>(dst, in[h]);
+          store_pack<S, C, E>(dst, val);
         } else {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             if ((cut_lo && e == 0) || (cut_hi && e == E - 1)) continue;
-            dst[e] = Codec<S, C>::store(in[h][e]);
+            dst[e] = Codec<S, C>::store(val[e]);
           }
         }
-        if constexpr (cx != 0) {
-          // link X of the node at an x wall returns into that node as XB
-          if (p.bbx && cx > 0 && xs + E == p.nx) {
-            C b = v[h][E - 1];
-            if (p.moving) b += C(L::wmul[X]) * wall_dot<L, X, C>(p, 1);
-            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + XB * astride(p)] = Codec<S, C>::store(b);
-          }
-          if (p.bbx && cx < 0 && xs == 0) {
-            C b = v[h][0];
-            if (p.moving) b += C(L::wmul[X]) * wall_dot<L, X, C>(p, 0);
-            f[slot<L::Q>(p, ln.rowbase) + XB * astride(p)] = Codec<S, C>::store(b);
-          }
-        }
-      }
-    } else {
-      // every node of this row sends link X across a y/z wall: it comes back
-      // into the same node as the opposite link
-      C cw = C(0);
-      if (p.moving) {
-        // corrections of every wall the link crosses (edges: the sum)
-        if (cy != 0 && (ln.y + cy < 0 || ln.y + cy >= p.ny))
-          cw += wall_dot<L, X, C>(p, 2 + (ln.y + cy < 0 ? 0 : 1));
-        if (cz != 0 && (ln.z + cz < 0 || ln.z + cz >= p.nz))
-          cw += wall_dot<L, X, C>(p, 4 + (ln.z + cz < 0 ? 0 : 1));
-      }
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (!ln.act[h]) continue;
-        const int64_t xs = ln.xh[h];
+      } else {
+        // every node of this row sends link A across a y/z wall: it comes
+        // back into the same node as the opposite link
         C bv[E];
+        if (!p.moving) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          bv[e] = v[h][e];
-          if (p.moving) {
-            C extra = cw;
-            if constexpr (cx != 0) {
-              if (p.bbx && cx > 0 && xs + e == p.nx - 1) extra += wall_dot<L, X, C>(p, 1);
-              if (p.bbx && cx < 0 && xs + e == 0) extra += wall_dot<L, X, C>(p, 0);
-            }
-            bv[e] += C(L::wmul[X]) * extra;
-          }
-        }
-        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + XB * astride(p), bv);
-      }
-    }
-  }
-
-  // Link A and its opposite from the same two sums; the rest link alone.
-  template <int A>
-  __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
-                                               const C (&own)[H][E][K], const C (&hv)[L::Q],
-                                               const Lane& ln) {
-    if constexpr (A < L::Q) {
-      constexpr int AB = opposite<L>(A);
-      static_assert(L::wmul[A] == L::wmul[AB], "opposite links share their weight");
-      constexpr C mul = C(L::wmul[A]);
-      if constexpr (AB == A) {
-        C v[H][E];
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-          for (int e = 0; e < E; ++e) v[h][e] = mul * link_even<L, ORDER, A, C>(own[h][e]);
-        emit<A>(f, p, v, hv, ln);
-      } else if constexpr (A < AB) {
-        C va[H][E], vb[H][E];
-#pragma unroll
-        for (int h = 0; h < H; ++h)
+          for (int e = 0; e < E; ++e) bv[e] = link_value<L, ORDER, A, C>(own[h][e]);
+        } else {
+          // corrections of every wall the link crosses (edges: the sum)
+          C cw = C(0);
+          if (cy != 0 && (ln.y + cy < 0 || ln.y + cy >= p.ny))
+            cw += wall_dot<L, A, C>(p, 2 + (ln.y + cy < 0 ? 0 : 1));
+          if (cz != 0 && (ln.z + cz < 0 || ln.z + cz >= p.nz))
+            cw += wall_dot<L, A, C>(p, 4 + (ln.z + cz < 0 ? 0 : 1));
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const C ev = link_even<L, ORDER, A, C>(own[h][e]);
-            const C od = link_odd<L, ORDER, A, C>(own[h][e]);
-            va[h][e] = mul * (ev + od);
-            vb[h][e] = mul * (ev - od);
+            C extra = cw;
+            if constexpr (cx != 0) {
+              if (p.bbx && cx > 0 && xs + e == p.nx - 1) extra += wall_dot<L, A, C>(p, 1);
+              if (p.bbx && cx < 0 && xs + e == 0) extra += wall_dot<L, A, C>(p, 0);
+            }
+            bv[e] = link_value_plus<L, ORDER, A, C>(own[h][e], extra);
           }
-        emit<A>(f, p, va, hv, ln);
-        emit<AB>(f, p, vb, hv, ln);
+        }
+        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
       }
-      links<A + 1>(f, p, own, hv, ln);
+      if constexpr (cx != 0) {
+        if (row_in && p.bbx) {
+          if (cx > 0 && xs + E == p.nx)
+            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + AB * astride(p)] = Codec<S, C>::store(
+                p.moving ? link_value_plus<L, ORDER, A, C>(own[h][E - 1], wall_dot<L, A, C>(p, 1))
+                         : link_value<L, ORDER, A, C>(own[h][E - 1]));
+          if (cx < 0 && xs == 0)
+            f[slot<L::Q>(p, ln.rowbase) + AB * astride(p)] = Codec<S, C>::store(
+                p.moving ? link_value_plus<L, ORDER, A, C>(own[h][0], wall_dot<L, A, C>(p, 0))
+                         : link_value<L, ORDER, A, C>(own[h][0]));
+        }
+      }
     }
   }
 
-  // Links entering the segment from the nodes just outside it: c_x > 0 from
-  // the left node, c_x < 0 from the right one.
-  template <int X>
-  __device__ __forceinline__ static void halo_values(const C (&hl)[K], const C (&hr)[K],
-                                                     C (&hv)[L::Q]) {
-    if constexpr (X < L::Q) {
-      if constexpr (L::c[X][0] > 0) hv[X] = link_value<L, ORDER, X, C>(hl);
-      else if constexpr (L::c[X][0] < 0) hv[X] = link_value<L, ORDER, X, C>(hr);
-      else hv[X] = C(0);
-      halo_values<X + 1>(hl, hr, hv);
+  template <int A>
+  __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
+                                               const C (&own)[H][E][K], const C (&left)[H][K],
+                                               const C (&right)[H][K], const Lane& ln) {
+    if constexpr (A < L::Q) {
+      link<A>(f, p, own, left, right, ln);
+      links<A + 1>(f, p, own, left, right, ln);
     }
   }
 
@@ -564,7 +484,7 @@ struct StreamCollide {
     const int64_t ms = slot<M>(p, idx);
 #pragma unroll
     for (int q = 0; q < M; ++q) mm[q] = m[ms + q * astride(p)];
-    post_collision<L, ORDER, C>(mm, p, k);
+    post_collision<L, ORDER, C, FD>(mm, p, k);
   }
 
   // One wavefront: row segment number `wave` of the domain (wave-uniform).
@@ -576,12 +496,11 @@ struct StreamCollide {
     const int64_t seg = wave % p.nseg;
     const int64_t row = wave / p.nseg;
     Lane ln;
-    ln.lane = lane;
     ln.y = row % p.ny;
     ln.z = row / p.ny;
     ln.rowbase = p.nx * row;
     const int64_t x0 = seg * W;
-    ln.xend = (x0 + W < p.nx) ? x0 + W : p.nx;
+    const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       ln.xh[h] = x0 + (int64_t)h * 64 * E + (int64_t)lane * E;
@@ -609,14 +528,35 @@ struct StreamCollide {
           C mm[M];
 #pragma unroll
           for (int q = 0; q < M; ++q) mm[q] = mv[h][q][e];
-          post_collision<L, ORDER, C>(mm, p, own[h][e]);
+          post_collision<L, ORDER, C, FD>(mm, p, own[h][e]);
         }
     }
-    // coefficients of the nodes just outside the segment (x0 - 1 and xend),
-    // where they exist (beyond an x wall the links from there are cut)
-    C hl[K], hr[K];
+    // x-neighbours of each chunk's first and last node
+    C left[H][K], right[H][K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) hl[q] = hr[q] = C(0);
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        left[h][q] = lane_from_below(own[h][E - 1][q]);
+        right[h][q] = lane_from_above(own[h][0][q]);
+      }
+    if constexpr (H > 1) {
+      // chunk boundaries inside the segment: lane 0 of chunk h follows lane
+      // 63 of chunk h-1
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if (h > 0) {
+            const C v = lane_bcast(own[h - 1][E - 1][q], 63);
+            if (lane == 0) left[h][q] = v;
+          }
+          if (h < H - 1) {
+            const C v = lane_bcast(own[h + 1][0][q], 0);
+            if (lane == 63) right[h][q] = v;
+          }
+        }
+    }
     if (lane == 0) {
       int64_t xl = x0 - 1;
       bool ok = true;
@@ -624,30 +564,28 @@ struct StreamCollide {
         if (p.bbx) ok = false;
         else xl = p.nx - 1;
       }
-      if (ok) load_coef(m, p, ln.rowbase + xl, hl);
+      if (ok) load_coef(m, p, ln.rowbase + xl, left[0]);
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      if (ln.act[h] && ln.xh[h] + E == ln.xend) {
-        int64_t xr = ln.xend;
+      if (ln.act[h] && ln.xh[h] + E == xend) {
+        int64_t xr = xend;
         bool ok = true;
         if (xr >= p.nx) {
           if (p.bbx) ok = false;
           else xr = 0;
         }
-        if (ok) load_coef(m, p, ln.rowbase + xr, hr);
+        if (ok) load_coef(m, p, ln.rowbase + xr, right[h]);
       }
     }
-    C hv[L::Q];
-    halo_values<0>(hl, hr, hv);
-    links<0>(f, p, own, hv, ln);
+    links<0>(f, p, own, left, right, ln);
   }
 };
 
-template <class L, int ORDER, typename S, typename C, int E, int H>
+template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  StreamCollide<L, ORDER, S, C, E, H>::run_wave(
+  StreamCollide<L, ORDER, S, C, E, H, FD>::run_wave(
       m, f, p, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 

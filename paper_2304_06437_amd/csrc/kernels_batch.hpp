@@ -45,14 +45,14 @@ __global__ __launch_bounds__(256) void k_moments_batch(const JobDesc<C>* __restr
     moments2_body<L, S, C, V>((const S*)J.f, (C*)J.m, J.p, i0);
 }
 
-template <class L, int ORDER, int SPECIES, typename S, typename C, int E, int H>
+template <class L, int ORDER, int SPECIES, typename S, typename C, int E, int H, bool FD = false>
 __global__ __launch_bounds__(256) void k_stream_collide_batch(const JobDesc<C>* __restrict__ jobs,
                                                               int njobs, int64_t total) {
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= total) return;  // wave-uniform
   const JobDesc<C>& J = jobs[job_of(jobs, njobs, w)];
   if constexpr (SPECIES == 1)
-    StreamCollide<L, ORDER, S, C, E, H>::run_wave((const C*)J.m, (S*)J.f, J.p, w - J.start);
+    StreamCollide<L, ORDER, S, C, E, H, FD>::run_wave((const C*)J.m, (S*)J.f, J.p, w - J.start);
   else
     StreamCollide2<L, S, C, E>::run_wave((const C*)J.m, (S*)J.f, J.p, J.cp, w - J.start);
 }
