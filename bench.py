@@ -68,6 +68,17 @@ def read_traffic(kernel: str):
     return float(m.group(1)) if m else None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(workload: str = "d3q19_tg", seconds_hint: float = 15.0):
     """Time the FP64 CPU oracle on a bounded sample of the same workload: the
     same lattice, flow and parameters on a smaller domain (the per-node work
@@ -115,6 +126,8 @@ def cpu_baseline(workload: str = "d3q19_tg", seconds_hint: float = 15.0):
                    "sigma 0.03, beta 0.7") +
                   f"; FP64 two-array oracle, {steps} steps ({dt:.1f} s) on a {n}-edge "
                   "domain; same per-node work as the benchmark",
+        "host_cpu": cpu_model(),
+        "nproc": os.cpu_count(),
     }
 
 

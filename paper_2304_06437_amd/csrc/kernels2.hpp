@@ -522,23 +522,12 @@ struct StreamCollide2 {
   }
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Remap so that XCD x runs a contiguous range of blocks (rows): the phi
-// rows a wavefront re-reads from its neighbours then mostly hit the same L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  constexpr int64_t X = 8;
-  const int64_t per = nb / X, rem = nb % X;
-  const int64_t x = b % X, k = b / X;
-  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
-
 template <class L, typename S, typename C, int E>
 __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m,
                                                          S* __restrict__ f, StepParams<C> p,
                                                          ColourParams<C> cp) {
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  StreamCollide2<L, S, C, E>::run_wave(m, f, p, cp,
-                                       blk * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  StreamCollide2<L, S, C, E>::run_wave(
+      m, f, p, cp, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.
