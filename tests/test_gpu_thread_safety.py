@@ -87,3 +87,35 @@ def test_moments_sweep_never_reads_moments(case):
     sim.close()
     for k in ("rho", "u", "pineq"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_distinct_handles_from_concurrent_host_threads():
+    """The library keeps no shared mutable state: simulations driven from
+    several host threads at once (each on its own stream) give bit for bit
+    the results of the same runs one after another."""
+    import threading
+
+    import torch
+
+    def one(i, case, out):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            sim = _setup(CASES[case], storage=("f32", "f16s", "f32", "f32")[i])
+            sim.step(60)
+            out[i] = sim.moments(phi=CASES[case]["species"] == 2)
+            sim.close()
+
+    order = list(range(len(CASES)))
+    seq = {}
+    for i in order:
+        one(i, i, seq)
+    par = {}
+    threads = [threading.Thread(target=one, args=(i, i, par)) for i in order]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert all(not t.is_alive() for t in threads)
+    for i in order:
+        for k in ("rho", "u", "pineq"):
+            assert np.array_equal(seq[i][k], par[i][k]), (i, k)
