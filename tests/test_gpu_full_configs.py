@@ -1,0 +1,139 @@
+"""The benchmark configurations at their full sizes, in the launch
+configurations the benchmark times (through the C ABI).
+
+Where the oracle cannot run the whole domain, outputs are checked one by one
+on their dependency cones (a node after s steps depends on the nodes within
+s links, 2 s with the colour gradient of two species), or through
+properties that hold at any size:
+  * D3Q19 256^3 channel, 2000 steps: the flow is one-dimensional in the
+    mean, so the plane-averaged velocity profile equals the oracle's run on
+    a 1 x 1 x 256 column started from the plane-averaged density;
+  * D3Q27 third order 512^3 Taylor-Green: sampled nodes after 8 steps;
+  * two species 256^3 with 64 droplets: sampled interface nodes after 6
+    steps, and mass / momentum conservation over the full 5000 steps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_06437_amd import inputs
+from paper_2304_06437_amd.sim import Simulation, make_params, max_rel, run
+
+pytestmark = pytest.mark.gpu
+
+
+def _cone(field, shape, centre, h):
+    """Periodic (2h+1)^3 block of a flat field (or of its D components)."""
+    nx, ny, nz = shape
+    idx = [np.arange(c - h, c + h + 1) % n for c, n in zip(centre, shape)]
+    if field.ndim == 2:
+        f3 = field.reshape((-1, nz, ny, nx))
+        return f3[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]].reshape(field.shape[0], -1)
+    f3 = field.reshape((nz, ny, nx))
+    return f3[idx[2]][:, idx[1]][:, :, idx[0]].reshape(-1)
+
+
+@pytest.mark.timeout(300)
+def test_channel_256_mean_profile_against_column_oracle():
+    n, steps, tau, g = 256, 2000, 0.6, 1e-6
+    rho, u = inputs.channel_noise(n, n, n, 3)
+    p = make_params(lattice=19, shape=(n, n, n), tau=tau, force=(g, 0.0, 0.0), bc=(0, 0, 1))
+    with Simulation(p) as sim:
+        sim.init(rho, u)
+        sim.step(steps)
+        got = sim.moments(rho=False, u=True, pineq=False, conserved=False)
+    prof = got["u"].reshape(3, n, n * n).mean(axis=2)  # plane means, one per z
+    q = oracle.Params(lattice=19, nx=1, ny=1, nz=n, tau=tau, force=(g, 0.0, 0.0), bb=(0, 0, 1))
+    ref = oracle.simulate(q, rho.reshape(n, n * n).mean(axis=1), np.zeros((3, n)), steps)
+    scale = np.abs(ref["u"][0]).max()
+    err = np.abs(prof - ref["u"]).max(axis=1) / scale
+    print(f"256^3 channel, 2000 steps: plane-mean u vs column oracle, max error / max u_x: "
+          f"x {err[0]:.2e}, y {err[1]:.2e}, z {err[2]:.2e}; bulk u_x {prof[0, n // 2]:.4e}, "
+          f"column u_z up to {np.abs(ref['u'][2]).max():.1e}")
+    # the plane-mean dynamics are the column's up to products of the noise
+    # (1e-4 squared), far below the FP32 bar
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_d3q27_third_order_512_sampled_against_oracle(storage):
+    n, steps, tau, u0 = 512, 8, 0.55, 0.02
+    shape = (n, n, n)
+    rho, u = inputs.taylor_green_3d(n, n, n, u0)
+    p = make_params(lattice=27, shape=shape, tau=tau, order=3, storage=storage)
+    got = run(p, rho, u, steps, pineq=False, conserved=False)
+    h = steps + 2
+    samples = [(0, 0, 0), (511, 511, 511), (255, 256, 17), (63, 64, 65), (1, 510, 300)]
+    worst, worst_rho = 0.0, 0.0
+    for (x, y, z) in samples:
+        q = oracle.Params(lattice=27, nx=2 * h + 1, ny=2 * h + 1, nz=2 * h + 1, tau=tau, order=3)
+        ref = oracle.simulate(q, _cone(rho, shape, (x, y, z), h), _cone(u, shape, (x, y, z), h),
+                              steps)
+        c = h + (2 * h + 1) * (h + (2 * h + 1) * h)
+        nidx = x + n * (y + n * z)
+        worst = max(worst, np.abs(got["u"][:, nidx] - ref["u"][:, c]).max() / u0)
+        worst_rho = max(worst_rho, abs(got["rho"][nidx] - ref["rho"][c]))
+    print(f"D3Q27 order 3 512^3 {storage}: sampled max |du|/u0 {worst:.3e}, |d rho| {worst_rho:.2e}")
+    if storage == "f32":
+        assert worst <= 1e-5 and worst_rho <= 1e-7
+    else:
+        assert worst <= 1e-2  # reported; 16-bit storage has no bar
+
+
+def _droplet_field(n=256, count=64, R=12.0):
+    centres = inputs.droplet_centres(n, count, R, gap=2.0, seed=7)
+    rho, u, phi = inputs.droplets(n, centres, R)
+    return centres, rho, u, phi
+
+
+@pytest.mark.timeout(300)
+def test_two_species_256_sampled_against_oracle():
+    n, steps, tau, sigma, beta, R = 256, 6, 1.0, 0.03, 0.7, 12.0
+    shape = (n, n, n)
+    centres, rho, u, phi = _droplet_field(n, 64, R)
+    p = make_params(lattice=19, shape=shape, tau=tau, species=2, sigma=sigma, beta=beta)
+    got = run(p, rho, u, steps, phi=phi, phi_out=True, pineq=False, conserved=False)
+    h = 2 * steps + 2
+    worst_u = worst_phi = 0.0
+    umax = 0.0
+    for c in centres[:6]:
+        # the node where the +x axis through the centre leaves the droplet
+        x, y, z = int(np.floor(c[0] + R)) % n, int(round(c[1])) % n, int(round(c[2])) % n
+        q = oracle.Params(lattice=19, nx=2 * h + 1, ny=2 * h + 1, nz=2 * h + 1, tau=tau,
+                          species=2, sigma=sigma, beta=beta)
+        ref = oracle.simulate(q, _cone(rho, shape, (x, y, z), h), _cone(u, shape, (x, y, z), h),
+                              steps, phi=_cone(phi, shape, (x, y, z), h))
+        k = h + (2 * h + 1) * (h + (2 * h + 1) * h)
+        nidx = x + n * (y + n * z)
+        worst_u = max(worst_u, np.abs(got["u"][:, nidx] - ref["u"][:, k]).max())
+        worst_phi = max(worst_phi, abs(got["phi"][nidx] - ref["phi"][k]))
+        umax = max(umax, np.abs(ref["u"][:, k]).max())
+    print(f"two species 256^3: sampled |du| {worst_u:.2e} (|u| up to {umax:.1e}), "
+          f"|d phi| {worst_phi:.2e}")
+    assert umax > 1e-5  # the samples sit where the interface drives a flow
+    assert worst_u <= 1e-4 * umax and worst_phi <= 1e-5
+
+
+@pytest.mark.timeout(300)
+def test_two_species_256_conservation_over_5000_steps():
+    n, steps = 256, 5000
+    _, rho, u, phi = _droplet_field(n, 64, 12.0)
+    N = n ** 3
+    p = make_params(lattice=19, shape=(n, n, n), tau=1.0, species=2, sigma=0.03, beta=0.7)
+    with Simulation(p) as sim:
+        sim.init(rho, u, phi)
+        c0 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
+        sim.step(steps)
+        c1 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
+    red0 = (rho * (1 + phi) / 2).sum()
+    d_total = abs(c1[0] - c0[0]) / N
+    d_red = abs(c1[4] - red0) / N
+    d_mom = np.abs(c1[1:4] - c0[1:4]).max() / N
+    print(f"two species 256^3, 5000 steps, per-node drift: total {d_total:.1e}, red {d_red:.1e}, "
+          f"momentum {d_mom:.1e}")
+    assert d_total <= 1e-8
+    assert d_mom <= 1e-8
+    # red populations are stored unshifted in FP32: their rounding walks the
+    # red mass by ~1e-9 per node and step at most
+    assert d_red <= 1e-9 * steps
