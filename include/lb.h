@@ -127,12 +127,15 @@ size_t lb_required_bytes(const lb_params* p);
 int lb_validate(const lb_params* p);
 
 /* Create a simulation on the current HIP device.
- *   dev_mem    device buffer of dev_bytes >= lb_required_bytes(p), owned by
- *              the caller and outliving the handle; or NULL, in which case the
- *              library allocates (hipMalloc) and frees the memory itself.
+ *   dev_mem    device buffer of dev_bytes >= lb_required_bytes(p), 256-byte
+ *              aligned, owned by the caller and outliving the handle; or
+ *              NULL, in which case the library allocates (hipMalloc) and
+ *              frees the memory itself.
  *   hip_stream hipStream_t to enqueue all work on (borrowed, may be NULL for
  *              the null stream).
- * The populations are zero (rest state) until lb_init. */
+ * LB_ENOMEM if dev_bytes is too small or the allocation fails, LB_EINVAL for
+ * a misaligned dev_mem.  The populations are zero (rest state) until
+ * lb_init. */
 int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_stream,
               lb_handle** out);
 
@@ -155,6 +158,8 @@ int lb_step(lb_handle* h, int64_t nsteps);
  * lb_sweep(h, 1); the step counter advances after which = 1.  For
  * instrumentation and for tests of the sweeps' data dependencies. */
 int lb_sweep(lb_handle* h, int which);
+/* (lb_init and lb_moments use the moment arrays as staging for their host
+ * transfers: after them, run which = 0 before a which = 1 sweep.) */
 
 /* Device layout of the handle's state, for tests and tools.  The population
  * region (species*Q arrays of the storage type: set 0 then set 1) starts at

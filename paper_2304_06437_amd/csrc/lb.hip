@@ -252,7 +252,11 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
     h->stream = (hipStream_t)hip_stream;
     h->v2 = choose_v2(p->nx, h->impl->v2max);
     if (dev_mem) {
-      if (dev_bytes < h->L.total || ((uintptr_t)dev_mem % kAlign) != 0) {
+      if (((uintptr_t)dev_mem % kAlign) != 0) {
+        delete h;
+        return LB_EINVAL;
+      }
+      if (dev_bytes < h->L.total) {
         delete h;
         return LB_ENOMEM;
       }

@@ -85,3 +85,20 @@ def test_moment_layout_after_moments_sweep():
     assert np.abs(mom[0] - (rho - 1.0)).max() < 1e-7
     for al in range(3):
         assert np.abs(mom[1 + al] - u[al]).max() < 1e-7
+
+
+def test_create_rejects_small_or_misaligned_buffers():
+    import torch
+
+    p = make_params(lattice=19, shape=(40, 24, 20))
+    need = lb.lb_required_bytes(p)
+    buf = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(lb.LbError) as e:
+        lb.lb_create(p, buf.data_ptr(), need - 256, stream)
+    assert e.value.status == lb.LB_ENOMEM
+    with pytest.raises(lb.LbError) as e:
+        lb.lb_create(p, buf.data_ptr() + 16, need, stream)
+    assert e.value.status == lb.LB_EINVAL
+    h = lb.lb_create(p, buf.data_ptr() + 256, need, stream)  # aligned, exact size
+    lb.lb_destroy(h)
