@@ -689,8 +689,10 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
         LB_TRY_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
         hipError_t le = launch_segment_step(b, seg);
         hipError_t ce = hipStreamEndCapture(b->stream, &gr);
-        if (le != hipSuccess) return status_of(le);
-        if (ce != hipSuccess) return status_of(ce);
+        if (le != hipSuccess || ce != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return status_of(le != hipSuccess ? le : ce);
+        }
         hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
         if (ie != hipSuccess) {
           (void)hipGraphDestroy(gr);
