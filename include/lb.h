@@ -228,6 +228,13 @@ int lb_batch_set_graphs(lb_batch* b, int enable);
 /* Destroy a batch executor (waits for its stream).  NULL is accepted. */
 int lb_batch_destroy(lb_batch* b);
 
+/* One-shot form of the above: advance handles[i] by nsteps[i] with a batch
+ * created on the handles' common stream for this call only (same rules and
+ * results as lb_batch_step; the batch's tables are allocated and freed
+ * inside the call).  LB_EINVAL also when the handles are on different
+ * streams. */
+int lb_step_batch(lb_handle* const* handles, const int64_t* nsteps, int count);
+
 /* ---- instrumentation ------------------------------------------------- */
 
 /* Start per-kernel timing: the next lb_step calls record HIP events around

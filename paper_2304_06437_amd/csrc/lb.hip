@@ -716,6 +716,18 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
   }
 }
 
+int lb_step_batch(lb_handle* const* hs, const int64_t* nsteps, int count) {
+  if (count < 0 || (count > 0 && (!hs || !nsteps))) return LB_EINVAL;
+  if (count == 0) return LB_OK;
+  if (!hs[0]) return LB_EINVAL;
+  lb_batch* b = nullptr;
+  int st = lb_batch_create(hs[0]->stream, &b);
+  if (st != LB_OK) return st;
+  st = lb_batch_step(b, hs, nsteps, count);
+  const int dst = lb_batch_destroy(b);
+  return st != LB_OK ? st : dst;
+}
+
 int lb_batch_destroy(lb_batch* b) {
   if (!b) return LB_OK;
   int st = LB_OK;

@@ -101,6 +101,8 @@ def load():
     lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.lb_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.lb_step_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.c_int]
     lib.lb_batch_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.lb_batch_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -261,6 +263,14 @@ def lb_batch_step(b, handles, nsteps):
     hs = (ctypes.c_void_p * n)(*[h.value for h in handles])
     ns = (ctypes.c_int64 * n)(*[int(k) for k in nsteps])
     _check(load().lb_batch_step(b, hs, ns, n), "lb_batch_step")
+
+
+def lb_step_batch(handles, nsteps):
+    """One-shot batched step of handles on one stream (see lb_batch_step)."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.value for h in handles])
+    ns = (ctypes.c_int64 * n)(*[int(k) for k in nsteps])
+    _check(load().lb_step_batch(hs, ns, n), "lb_step_batch")
 
 
 def lb_batch_set_graphs(b, enable: bool):

@@ -127,3 +127,18 @@ def test_serving_loop_end_to_end():
         alone = _batch_run([s])[0]
         got = rep.results[s.job_id].moments
         assert np.array_equal(got["u"], alone["u"]), s.job_id
+
+
+def test_one_shot_step_batch_equals_batch_object():
+    import torch
+
+    with torch.cuda.stream(_stream()):
+        sims = [_sim(s) for s in MIX[:4]]
+        lb.lb_step_batch([s.handle for s in sims], [s.steps for s in MIX[:4]])
+        got = [sim.moments(phi=False) for sim in sims]
+        for sim in sims:
+            sim.close()
+    ref = _batch_run(MIX[:4])
+    for a, b in zip(got, ref):
+        for k in ("rho", "u", "pineq"):
+            assert np.array_equal(a[k], b[k])
