@@ -92,6 +92,7 @@ class ServeReport:
     max_active: int
     peak_bytes: int
     chunks: int = 0
+    phase_s: dict = field(default_factory=dict)  # host time: create, step, read, idle
 
     def _tts(self):
         return np.array([r.time_to_solution for r in self.results if r.status == "done"])
@@ -122,6 +123,7 @@ class ServeReport:
             "p99_s": round(self.p99, 4), "aggregate_MLUPS": round(self.mlups, 1),
             "makespan_s": round(self.makespan, 3), "max_active": self.max_active,
             "peak_GB": round(self.peak_bytes / 1e9, 3), "chunks": self.chunks,
+            "phase_s": {k: round(v, 3) for k, v in self.phase_s.items()},
         }
 
 
@@ -223,6 +225,7 @@ class Server:
         futures = {}
         used = peak = 0
         max_active = chunks = 0
+        phase = {"create": 0.0, "step": 0.0, "read": 0.0, "idle": 0.0}
         t0 = self.clock()
 
         def now():
@@ -258,6 +261,7 @@ class Server:
                     break
                 queue.popleft()
                 res.admitted = now()
+                tc = self.clock()
                 try:
                     fut = futures.pop(spec.job_id, None)
                     if fut is not None:
@@ -268,18 +272,24 @@ class Server:
                     res.status, res.error, res.finished = "failed", repr(e), now()
                     results[spec.job_id] = res
                     continue
+                finally:
+                    phase["create"] += self.clock() - tc
                 used += need
                 peak = max(peak, used)
                 active.append(_Active(spec, handle, need, res))
             max_active = max(max_active, len(active))
             if not active:
                 if pending and not queue:
+                    ti = self.clock()
                     self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                    phase["idle"] += self.clock() - ti
                 continue
             # one chunk for every resident simulation
             nsteps = [min(self.chunk, a.remaining) for a in active]
+            ts = self.clock()
             try:
                 self.backend.step([a.handle for a in active], nsteps)
+                phase["step"] += self.clock() - ts
             except Exception as e:
                 # a launch failure poisons the whole batch: fail every member
                 for a in active:
@@ -296,6 +306,7 @@ class Server:
                 if a.remaining > 0:
                     still.append(a)
                     continue
+                tr = self.clock()
                 try:
                     out = self.backend.read(a.handle, a.spec)
                     a.result.status = "done"
@@ -304,13 +315,14 @@ class Server:
                         a.result.moments = out
                 except Exception as e:
                     a.result.status, a.result.error = "failed", repr(e)
+                phase["read"] += self.clock() - tr
                 a.result.finished = now()
                 results[a.spec.job_id] = a.result
                 self._release(a)
                 used -= a.nbytes
             active = still
         ordered = [results[s.job_id] for s in sorted(specs, key=lambda s: s.job_id)]
-        return ServeReport(ordered, now(), max_active, peak, chunks)
+        return ServeReport(ordered, now(), max_active, peak, chunks, phase)
 
     def _release(self, a):
         try:
