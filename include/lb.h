@@ -117,10 +117,12 @@ void lb_params_default(lb_params* p);
 
 /* Exact number of device bytes lb_create needs for these parameters:
  * populations (species * Q arrays) + moments (M arrays) of npad nodes each,
- * npad = N rounded up to the layout's block size (see lb_layout), each
- * region 256-byte aligned, + 64 KiB of FP64 reduction scratch (Section 4
- * counts 15 arrays per node for D2Q9 and 29 for D3Q19 in single precision).
- * Returns 0 for invalid parameters. */
+ * npad = px * ny * nz rounded up to the layout's block size, where the row
+ * pitch px is nx rounded up to a multiple of the stream-collide sweep's
+ * vector chunk (1 to 8 nodes; see lb_layout), each region 256-byte aligned,
+ * + 64 KiB of FP64 reduction scratch (Section 4 counts 15 arrays per node
+ * for D2Q9 and 29 for D3Q19 in single precision).  Returns 0 for invalid
+ * parameters. */
 size_t lb_required_bytes(const lb_params* p);
 
 /* Validate parameters without touching the device. */
@@ -164,14 +166,18 @@ int lb_sweep(lb_handle* h, int which);
 /* Device layout of the handle's state, for tests and tools.  The population
  * region (species*Q arrays of the storage type: set 0 then set 1) starts at
  * byte pop_offset of the device buffer, the moment region (M arrays of the
- * compute type: drho, j, Pi^neq [, phi]) at moment_offset.  Both are blocked
- * structures of arrays over padded_nodes >= N nodes: with B = block_nodes (a
- * power of two), element (a, n) of a region of NA arrays is element
- * (n / B) * NA * B + a * B + n % B of that region.  Populations are stored
- * shifted (f_a - t_a rho0 for set 0).  The layout is internal: it may change
- * between versions, and only the moments are part of the interface. */
+ * compute type: drho, j, Pi^neq [, phi]) at moment_offset.  Node (x, y, z)
+ * is storage node n = x + row_pitch * (y + ny * z), row_pitch >= nx (nx
+ * rounded up so that the stream-collide sweep's vectors stay aligned; the
+ * storage nodes x >= nx of a row are padding and hold zero populations).
+ * Both regions are blocked structures of arrays over padded_nodes storage
+ * nodes: with B = block_nodes (a power of two), element (a, n) of a region of
+ * NA arrays is element (n / B) * NA * B + a * B + n % B of that region.
+ * Populations are stored shifted (f_a - t_a rho0 for set 0).  The layout is
+ * internal: it may change between versions, and only the moments are part
+ * of the interface. */
 int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
-              int64_t* block_nodes, int64_t* padded_nodes);
+              int64_t* block_nodes, int64_t* padded_nodes, int64_t* row_pitch);
 
 /* Wait for all work enqueued on the handle's stream. */
 int lb_synchronize(lb_handle* h);

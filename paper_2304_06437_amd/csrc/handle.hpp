@@ -20,7 +20,9 @@ constexpr int kRedBlocks = 1024;  // blocks of the conservation reduction
 struct Layout {
   int Q = 0, D = 0, M = 0, species = 1;
   size_t ssize = 0, csize = 0;  // bytes per stored population / per moment
-  int64_t N = 0, npad = 0;
+  int64_t N = 0, npad = 0;      // lattice nodes; storage nodes padded to whole blocks
+  int64_t px = 0;               // row pitch: storage nodes per x-row (>= nx)
+  int v2 = 1;                   // nodes per lane of the stream-collide sweep
   int lb = 10;                  // log2 of the block size of the array layout
   size_t f_off = 0, m_off = 0, r_off = 0, total = 0;
 };
@@ -54,7 +56,8 @@ namespace lbk {
 
 struct Impl {
   int v1;
-  int v2max;
+  int v2max;  // widest lane vector (nodes per lane) of the stream-collide sweep
+  int emax;   // widest contiguous chunk of it; rows are padded to a multiple
   hipError_t (*moments)(const lb_handle*);
   hipError_t (*stream_collide)(const lb_handle*);
   hipError_t (*init)(const lb_handle*, const double*, int64_t, int64_t);
@@ -193,7 +196,8 @@ struct ImplT {
     return hipErrorInvalidValue;
   }
   static const Impl* get() {
-    static const Impl impl = {V1,           V2MAX,          &moments,       &stream_collide,
+    static const Impl impl = {V1,           V2MAX,          EMAX < V2MAX ? EMAX : V2MAX,
+                              &moments,     &stream_collide,
                               &init,        &readout,       &conserved,     sizeof(JobDesc<C>),
                               &fill_job_desc<C>, &units_moments, &units_sc, &batch_moments,
                               &batch_sc};
@@ -296,7 +300,8 @@ struct ImplT2 {
     return hipErrorInvalidValue;
   }
   static const Impl* get() {
-    static const Impl impl = {V1,           V2MAX,          &moments,       &stream_collide,
+    static const Impl impl = {V1,           V2MAX,          V2MAX,
+                              &moments,     &stream_collide,
                               &init,        &readout,       &conserved,     sizeof(JobDesc<C>),
                               &fill_job_desc<C>, &units_moments, &units_sc, &batch_moments,
                               &batch_sc};

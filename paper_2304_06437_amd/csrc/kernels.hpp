@@ -41,6 +41,7 @@ namespace lbk {
 template <typename C>
 struct StepParams {
   int64_t nx, ny, nz;
+  int64_t px;          // row pitch: storage nodes per x-row (nx rounded up)
   int64_t npad;        // padded node count (a multiple of the block size)
   int64_t nseg;        // row segments per x-row in stream_collide
   int32_t bbx, bby, bbz;
@@ -76,6 +77,15 @@ __device__ __forceinline__ int64_t slot(const StepParams<C>& p, int64_t n) {
 template <typename C>
 __device__ __forceinline__ int64_t astride(const StepParams<C>& p) {
   return int64_t(1) << p.lb;
+}
+
+// Storage node of lattice node n = x + nx (y + ny z).  Rows are px >= nx
+// storage nodes apart, so that every row starts on a vector boundary; nodes
+// x in [nx, px) of a row are padding, never written after creation (zero).
+template <typename C>
+__device__ __forceinline__ int64_t node_at(const StepParams<C>& p, int64_t n) {
+  if (p.px == p.nx) return n;
+  return n + (n / p.nx) * (p.px - p.nx);
 }
 
 // -------------------------------------------------------------------------
@@ -358,7 +368,10 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 // chunks of 64 E nodes; lane l owns nodes h*64E + l*E + e (e < E) of chunk h.
 // Every vector load or store instruction therefore covers 64 E contiguous
 // nodes (16 bytes per lane for E = 4 floats): whole cache lines per
-// instruction.
+// instruction.  Rows are px apart, nx rounded up to a multiple of E, so
+// every vector is aligned; where px > nx the vector holding the row's last
+// node (position tl < E - 1) reads padding moments but stores only its
+// first tl + 1 nodes.
 // -------------------------------------------------------------------------
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
 struct StreamCollide {
@@ -370,7 +383,8 @@ struct StreamCollide {
 
   struct Lane {
     int64_t xh[H];    // first node of this lane's chunk h
-    bool act[H];      // chunk h inside the row
+    bool act[H];      // chunk h starts inside the row
+    int tl[H];        // position of the row's last node x = nx - 1 in chunk h, E if absent
     int64_t y, z, rowbase;
   };
 
@@ -395,35 +409,47 @@ struct StreamCollide {
         else tz = (tz < 0) ? p.nz - 1 : 0;
       }
     }
-    const int64_t trow = p.nx * (ty + p.ny * tz);
+    const int64_t trow = p.px * (ty + p.ny * tz);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       if (!ln.act[h]) continue;
       const int64_t xs = ln.xh[h];
+      const int tl = ln.tl[h];
       if (row_in) {
         // value arriving at x (this lane's nodes) from source x - cx of this row
         C val[E];
+        if constexpr (cx == 0) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if constexpr (cx == 0) {
-            val[e] = link_value<L, ORDER, A, C>(own[h][e]);
-          } else if constexpr (cx > 0) {
+          for (int e = 0; e < E; ++e) val[e] = link_value<L, ORDER, A, C>(own[h][e]);
+        } else if constexpr (cx > 0) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
             val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[h][e > 0 ? e - 1 : 0])
                              : link_value<L, ORDER, A, C>(left[h]);
-          } else {
-            val[e] = (e < E - 1) ? link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0])
-                                 : link_value<L, ORDER, A, C>(right[h]);
+        } else {
+          // source x + 1; for the last node of a padded row (tl < E - 1) that
+          // is the node after the row end, which right holds
+          const C rv = link_value<L, ORDER, A, C>(right[h]);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (e < E - 1) {
+              const C v = link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0]);
+              val[e] = (e == tl) ? rv : v;
+            } else {
+              val[e] = rv;
+            }
           }
         }
         S* dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
-        const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);          // source x = -1
-        const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);    // source x = nx
-        if (!(cut_lo || cut_hi)) {
+        const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);   // source x = -1
+        const bool cut_hi = (cx < 0) && p.bbx && (tl < E);    // source x = nx
+        if (!(cut_lo || cut_hi || tl < E - 1)) {
           store_pack<S, C, E>(dst, val);
         } else {
+          // row ends: skip the links a wall supplies and the padding
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            if ((cut_lo && e == 0) || (cut_hi && e == E - 1)) continue;
+            if (e > tl || (cut_lo && e == 0) || (cut_hi && e == tl)) continue;
             dst[e] = Codec<S, C>::store(val[e]);
           }
         }
@@ -451,14 +477,26 @@ struct StreamCollide {
             bv[e] = link_value_plus<L, ORDER, A, C>(own[h][e], extra);
           }
         }
-        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
+        S* dst = f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p);
+        if (tl >= E - 1) {
+          store_pack<S, C, E>(dst, bv);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (e <= tl) dst[e] = Codec<S, C>::store(bv[e]);
+        }
       }
       if constexpr (cx != 0) {
         if (row_in && p.bbx) {
-          if (cx > 0 && xs + E == p.nx)
-            f[slot<L::Q>(p, ln.rowbase + p.nx - 1) + AB * astride(p)] = Codec<S, C>::store(
-                p.moving ? link_value_plus<L, ORDER, A, C>(own[h][E - 1], wall_dot<L, A, C>(p, 1))
-                         : link_value<L, ORDER, A, C>(own[h][E - 1]));
+          if (cx > 0 && tl < E) {
+            // this vector holds x = nx - 1, node tl
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+              if (e == tl)
+                f[slot<L::Q>(p, ln.rowbase + xs + e) + AB * astride(p)] = Codec<S, C>::store(
+                    p.moving ? link_value_plus<L, ORDER, A, C>(own[h][e], wall_dot<L, A, C>(p, 1))
+                             : link_value<L, ORDER, A, C>(own[h][e]));
+          }
           if (cx < 0 && xs == 0)
             f[slot<L::Q>(p, ln.rowbase) + AB * astride(p)] = Codec<S, C>::store(
                 p.moving ? link_value_plus<L, ORDER, A, C>(own[h][0], wall_dot<L, A, C>(p, 0))
@@ -498,13 +536,15 @@ struct StreamCollide {
     Lane ln;
     ln.y = row % p.ny;
     ln.z = row / p.ny;
-    ln.rowbase = p.nx * row;
+    ln.rowbase = p.px * row;
     const int64_t x0 = seg * W;
     const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       ln.xh[h] = x0 + (int64_t)h * 64 * E + (int64_t)lane * E;
       ln.act[h] = ln.xh[h] < p.nx;
+      const int64_t rem = p.nx - 1 - ln.xh[h];
+      ln.tl[h] = (rem >= 0 && rem < E) ? (int)rem : E;
     }
 
     C own[H][E][K];
@@ -568,7 +608,7 @@ struct StreamCollide {
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      if (ln.act[h] && ln.xh[h] + E == xend) {
+      if (ln.act[h] && ln.xh[h] + E >= xend) {
         int64_t xr = xend;
         bool ok = true;
         if (xr >= p.nx) {
@@ -623,7 +663,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ stage, 
   }
   C k[CL::K];
   post_collision<L, ORDER, C>(mm, q, k);
-  init_links<L, ORDER, S, C, 0>(f, astride(p), slot<L::Q>(p, n0 + i), k);
+  init_links<L, ORDER, S, C, 0>(f, astride(p), slot<L::Q>(p, node_at(p, n0 + i)), k);
 }
 
 // -------------------------------------------------------------------------
@@ -637,9 +677,8 @@ __global__ __launch_bounds__(256) void k_readout(const S* __restrict__ f, double
   constexpr int D = L::D;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
-  const int64_t n = n0 + i;
   C s[L::Q], me[ML::M];
-  const int64_t fs = slot<L::Q>(p, n);
+  const int64_t fs = slot<L::Q>(p, node_at(p, n0 + i));
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) s[a] = Codec<S, C>::load(f[fs + a * astride(p)]);
   node_moments<L, C>(s, p, me);
@@ -664,7 +703,7 @@ __global__ __launch_bounds__(256) void k_conserved(const S* __restrict__ f,
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-    const int64_t fs = slot<L::Q>(p, n);
+    const int64_t fs = slot<L::Q>(p, node_at(p, n));
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
       const double s = (double)Codec<S, C>::load(f[fs + a * astride(p)]);

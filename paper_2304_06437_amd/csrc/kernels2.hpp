@@ -148,7 +148,7 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
   using ML = MomentLayout<L>;
   using XL = ColourLayout<L>;
   constexpr int D = L::D;
-  const int64_t n = x + p.nx * (y + p.ny * z);
+  const int64_t n = x + p.px * (y + p.ny * z);
   C mm[ML::M];
 #pragma unroll
   for (int q = 0; q < ML::M; ++q) mm[q] = m[slot<ML::M + 1>(p, n) + q * astride(p)];
@@ -182,7 +182,7 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
         if (p.bbz) inside = false;
         else tz = (tz < 0) ? p.nz - 1 : 0;
       }
-      const int64_t tb = p.nx * (ty + p.ny * tz);
+      const int64_t tb = p.px * (ty + p.ny * tz);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         if (!has[dx + 1]) continue;
@@ -266,11 +266,13 @@ struct StreamCollide2 {
   static constexpr int KT = XL::KT;
   static constexpr int W = 64 * E;
 
+  // tl: position of the row's last node x = nx - 1 in this lane's vector,
+  // E if the vector does not hold it (nodes after it are padding).
   template <int A>
   __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
                                               const C (&own)[E][KT], const C (&left)[KT],
-                                              const C (&right)[KT], int64_t xs, int64_t y,
-                                              int64_t z, int64_t rowbase) {
+                                              const C (&right)[KT], int64_t xs, int tl,
+                                              int64_t y, int64_t z, int64_t rowbase) {
     constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
     constexpr int AB = opposite<L>(A);
     int64_t ty = y + cy, tz = z + cz;
@@ -299,17 +301,29 @@ struct StreamCollide2 {
           else colour_link<L, A, C>(right, gv[e], rv[e]);
         }
       }
+      if constexpr (cx < 0 && E > 1) {
+        // the last node of a padded row takes source x + 1 from right
+        C gr, rr;
+        colour_link<L, A, C>(right, gr, rr);
+#pragma unroll
+        for (int e = 0; e < E - 1; ++e)
+          if (e == tl) {
+            gv[e] = gr;
+            rv[e] = rr;
+          }
+      }
       // the E nodes from t on lie in one block
-      const int64_t t = slot<2 * L::Q>(p, p.nx * (ty + p.ny * tz) + xs);
+      const int64_t t = slot<2 * L::Q>(p, p.px * (ty + p.ny * tz) + xs);
       const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);
-      const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);
-      if (!(cut_lo || cut_hi)) {
+      const bool cut_hi = (cx < 0) && p.bbx && (tl < E);
+      if (!(cut_lo || cut_hi || tl < E - 1)) {
         store_pack<S, C, E>(fr0 + t, gv);
         store_pack<S, C, E>(fr1 + t, rv);
       } else {
+        // row ends: skip the links a wall supplies and the padding
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if ((cut_lo && e == 0) || (cut_hi && e == E - 1)) continue;
+          if (e > tl || (cut_lo && e == 0) || (cut_hi && e == tl)) continue;
           fr0[t + e] = Codec<S, C>::store(gv[e]);
           fr1[t + e] = Codec<S, C>::store(rv[e]);
         }
@@ -319,20 +333,36 @@ struct StreamCollide2 {
 #pragma unroll
       for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], gv[e], rv[e]);
       const int64_t t = slot<2 * L::Q>(p, rowbase + xs);
-      store_pack<S, C, E>(f + t + AB * astride(p), gv);
-      store_pack<S, C, E>(f + t + (L::Q + AB) * astride(p), rv);
+      if (tl >= E - 1) {
+        store_pack<S, C, E>(f + t + AB * astride(p), gv);
+        store_pack<S, C, E>(f + t + (L::Q + AB) * astride(p), rv);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (e <= tl) {
+            f[t + e + AB * astride(p)] = Codec<S, C>::store(gv[e]);
+            f[t + e + (L::Q + AB) * astride(p)] = Codec<S, C>::store(rv[e]);
+          }
+      }
     }
     if constexpr (cx != 0) {
       if (row_in && p.bbx) {
-        int e = -1;
-        int64_t xw = -1;
-        if (cx > 0 && xs + E == p.nx) { e = E - 1; xw = p.nx - 1; }
-        if (cx < 0 && xs == 0) { e = 0; xw = 0; }
-        if (e >= 0) {
+        // x walls: the node next to the wall gets the link back reversed
+        if (cx > 0 && tl < E) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (e == tl) {
+              C g, r;
+              colour_link<L, A, C>(own[e], g, r);
+              const int64_t t = slot<2 * L::Q>(p, rowbase + xs + e);
+              f[t + AB * astride(p)] = Codec<S, C>::store(g);
+              f[t + (L::Q + AB) * astride(p)] = Codec<S, C>::store(r);
+            }
+        }
+        if (cx < 0 && xs == 0) {
           C g, r;
-          if (e == 0) colour_link<L, A, C>(own[0], g, r);
-          else colour_link<L, A, C>(own[E - 1], g, r);
-          const int64_t t = slot<2 * L::Q>(p, rowbase + xw);
+          colour_link<L, A, C>(own[0], g, r);
+          const int64_t t = slot<2 * L::Q>(p, rowbase);
           f[t + AB * astride(p)] = Codec<S, C>::store(g);
           f[t + (L::Q + AB) * astride(p)] = Codec<S, C>::store(r);
         }
@@ -343,11 +373,11 @@ struct StreamCollide2 {
   template <int A>
   __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
                                                const C (&own)[E][KT], const C (&left)[KT],
-                                               const C (&right)[KT], int64_t xs, int64_t y,
-                                               int64_t z, int64_t rowbase) {
+                                               const C (&right)[KT], int64_t xs, int tl,
+                                               int64_t y, int64_t z, int64_t rowbase) {
     if constexpr (A < L::Q) {
-      link<A>(f, p, own, left, right, xs, y, z, rowbase);
-      links<A + 1>(f, p, own, left, right, xs, y, z, rowbase);
+      link<A>(f, p, own, left, right, xs, tl, y, z, rowbase);
+      links<A + 1>(f, p, own, left, right, xs, tl, y, z, rowbase);
     }
   }
 
@@ -361,11 +391,13 @@ struct StreamCollide2 {
     const int64_t seg = wave % p.nseg;
     const int64_t row = wave / p.nseg;
     const int64_t y = row % p.ny, z = row / p.ny;
-    const int64_t rowbase = p.nx * row;
+    const int64_t rowbase = p.px * row;
     const int64_t x0 = seg * W;
     const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
     const int64_t xs = x0 + (int64_t)lane * E;
     const bool act = xs < p.nx;
+    const int64_t rem = p.nx - 1 - xs;
+    const int tl = (rem >= 0 && rem < E) ? (int)rem : E;
 
     C own[E][KT];
     C phio[E];
@@ -427,7 +459,7 @@ struct StreamCollide2 {
           if (p.bbz) inside = false;
           else tz = (tz < 0) ? p.nz - 1 : 0;
         }
-        const int64_t tb = p.nx * (ty + p.ny * tz);
+        const int64_t tb = p.px * (ty + p.ny * tz);
         C pv[E];
         if (inside) {
           if (act) load_plain<C, E, false>(m + phi_index<L>(p, tb + xs), pv);
@@ -443,14 +475,14 @@ struct StreamCollide2 {
         C pr = lane_from_above(pv[0]);
         if (inside) {
           if (lane == 0) pl = phi_at<L, C>(m, p, tb, x0, -1, phio[0]);
-          if (act && xs + E == xend) pr = phi_at<L, C>(m, p, tb, xend - 1, 1, phio[E - 1]);
+          if (act && xs + E >= xend) pr = phi_at<L, C>(m, p, tb, xend - 1, 1, phio[E - 1]);
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           C vals[3];
           vals[1] = pv[e];
           vals[0] = (e > 0) ? pv[e > 0 ? e - 1 : 0] : pl;
-          vals[2] = (e < E - 1) ? pv[e < E - 1 ? e + 1 : 0] : pr;
+          vals[2] = (e < E - 1 && e != tl) ? pv[e < E - 1 ? e + 1 : 0] : pr;
           if (!inside) {
             // the row lies beyond a y/z wall: every neighbour takes the own value
             vals[0] = vals[1] = vals[2] = phio[e];
@@ -508,7 +540,7 @@ struct StreamCollide2 {
       }
       if (ok) colour_state_scalar<L, C>(m, p, cp, xl, y, z, left);
     }
-    if (act && xs + E == xend) {
+    if (act && xs + E >= xend) {
       int64_t xr = xend;
       bool ok = true;
       if (xr >= p.nx) {
@@ -518,7 +550,7 @@ struct StreamCollide2 {
       if (ok) colour_state_scalar<L, C>(m, p, cp, xr, y, z, right);
     }
     if (!act) return;
-    links<0>(f, p, own, left, right, xs, y, z, rowbase);
+    links<0>(f, p, own, left, right, xs, tl, y, z, rowbase);
   }
 };
 
@@ -564,7 +596,7 @@ __global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage,
   }
   C k[CoefLayout<L, 2>::K];
   post_collision<L, 2, C>(mm, q, k);
-  init2_links<L, S, C, 0>(f, astride(p), slot<2 * L::Q>(p, n0 + i), k, p.rho0, xr);
+  init2_links<L, S, C, 0>(f, astride(p), slot<2 * L::Q>(p, node_at(p, n0 + i)), k, p.rho0, xr);
 }
 
 // Read-out: rho, u, Pi^neq of the mixture and phi; (2 + D + D(D+1)/2) x cnt.
@@ -575,10 +607,9 @@ __global__ __launch_bounds__(256) void k_readout2(const S* __restrict__ f, doubl
   constexpr int D = L::D;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
-  const int64_t n = n0 + i;
   C s[L::Q], me[ML::M];
   C rr = C(0);
-  const int64_t fs = slot<2 * L::Q>(p, n);
+  const int64_t fs = slot<2 * L::Q>(p, node_at(p, n0 + i));
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) {
     s[a] = Codec<S, C>::load(f[fs + a * astride(p)]);
@@ -605,7 +636,7 @@ __global__ __launch_bounds__(256) void k_conserved2(const S* __restrict__ f,
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-    const int64_t fs = slot<2 * L::Q>(p, n);
+    const int64_t fs = slot<2 * L::Q>(p, node_at(p, n));
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
       const double s = (double)Codec<S, C>::load(f[fs + a * astride(p)]);

@@ -129,27 +129,6 @@ int validate(const lb_params* p) {
   return LB_OK;
 }
 
-Layout layout_of(const lb_params* p) {
-  Layout L;
-  L.Q = lattice_q(p->lattice);
-  L.D = p->lattice == LB_D2Q9 ? 2 : 3;
-  L.M = 1 + L.D + L.D * (L.D + 1) / 2 + (p->species == 2 ? 1 : 0);  // + phi
-  L.species = p->species;
-  L.ssize = p->storage == LB_STORE_F64 ? 8 : p->storage == LB_STORE_F32 ? 4 : 2;
-  L.csize = p->compute == LB_COMPUTE_F64 ? 8 : 4;
-  L.N = p->nx * p->ny * p->nz;
-  int lb = 10;  // block of B = 2^lb nodes: 32 KiB of populations, >= 1024 nodes
-  while ((int64_t(1) << lb) < L.N && (int64_t(1) << lb) * (int64_t)L.ssize < 32768) ++lb;
-  L.lb = lb;
-  const int64_t B = int64_t(1) << lb;
-  L.npad = (L.N + B - 1) / B * B;
-  L.f_off = 0;
-  L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
-  L.r_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
-  L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
-  return L;
-}
-
 const Impl* select_impl(const lb_params* p) {
   switch (p->lattice) {
     case LB_D2Q9: return impl_d2q9(p->storage, p->species);
@@ -159,13 +138,43 @@ const Impl* select_impl(const lb_params* p) {
   return nullptr;
 }
 
-// Nodes per lane of the stream-collide sweep: the widest V <= vmax that
-// divides nx (aligned V-wide vector access) and still fills a wavefront
-// (64 V <= nx); V = 1 otherwise.
+// Nodes per lane of the stream-collide sweep: the narrowest V <= vmax that
+// needs no more wavefronts per x-row (64 V nodes each) than vmax does.  A
+// wider vector moves more bytes per instruction, but a row split over fewer
+// wavefronts with most lanes busy beats one wide vector on a few lanes.
 int choose_v2(int64_t nx, int vmax) {
-  for (int v = vmax; v >= 1; v >>= 1)
-    if (nx % v == 0 && 64 * v <= nx) return v;
-  return 1;
+  const int64_t fewest = (nx + 64 * vmax - 1) / (64 * vmax);
+  for (int v = 1; v < vmax; v <<= 1)
+    if ((nx + 64 * v - 1) / (64 * v) == fewest) return v;
+  return vmax;
+}
+
+Layout layout_of(const lb_params* p) {
+  Layout L;
+  L.Q = lattice_q(p->lattice);
+  L.D = p->lattice == LB_D2Q9 ? 2 : 3;
+  L.M = 1 + L.D + L.D * (L.D + 1) / 2 + (p->species == 2 ? 1 : 0);  // + phi
+  L.species = p->species;
+  L.ssize = p->storage == LB_STORE_F64 ? 8 : p->storage == LB_STORE_F32 ? 4 : 2;
+  L.csize = p->compute == LB_COMPUTE_F64 ? 8 : 4;
+  L.N = p->nx * p->ny * p->nz;
+  // rows padded to a whole number of the sweep's contiguous lane chunks, so
+  // that every vector access is aligned
+  const Impl* impl = select_impl(p);
+  L.v2 = impl ? choose_v2(p->nx, impl->v2max) : 1;
+  const int64_t e = impl ? std::min(L.v2, impl->emax) : 1;
+  L.px = (p->nx + e - 1) / e * e;
+  const int64_t ns = L.px * p->ny * p->nz;  // storage nodes
+  int lb = 10;  // block of B = 2^lb nodes: 32 KiB of populations, >= 1024 nodes
+  while ((int64_t(1) << lb) < ns && (int64_t(1) << lb) * (int64_t)L.ssize < 32768) ++lb;
+  L.lb = lb;
+  const int64_t B = int64_t(1) << lb;
+  L.npad = (ns + B - 1) / B * B;
+  L.f_off = 0;
+  L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
+  L.r_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
+  L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
+  return L;
 }
 
 template <typename C>
@@ -173,6 +182,7 @@ void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) 
   q.nx = p->nx;
   q.ny = p->ny;
   q.nz = p->nz;
+  q.px = L.px;
   q.npad = L.npad;
   q.nseg = (p->nx + 64 * v2 - 1) / (64 * v2);
   q.bbx = p->bc[0] == LB_BOUNCEBACK;
@@ -250,7 +260,7 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
       return LB_EUNSUPPORTED;
     }
     h->stream = (hipStream_t)hip_stream;
-    h->v2 = choose_v2(p->nx, h->impl->v2max);
+    h->v2 = h->L.v2;
     if (dev_mem) {
       if (((uintptr_t)dev_mem % kAlign) != 0) {
         delete h;
@@ -367,12 +377,14 @@ int lb_sweep(lb_handle* h, int which) {
 }
 
 int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
-              int64_t* block_nodes, int64_t* padded_nodes) {
-  if (!h || !pop_offset || !moment_offset || !block_nodes || !padded_nodes) return LB_EINVAL;
+              int64_t* block_nodes, int64_t* padded_nodes, int64_t* row_pitch) {
+  if (!h || !pop_offset || !moment_offset || !block_nodes || !padded_nodes || !row_pitch)
+    return LB_EINVAL;
   *pop_offset = h->L.f_off;
   *moment_offset = h->L.m_off;
   *block_nodes = int64_t(1) << h->L.lb;
   *padded_nodes = h->L.npad;
+  *row_pitch = h->L.px;
   return LB_OK;
 }
 

@@ -99,7 +99,8 @@ def load():
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.lb_sweep.argtypes = [H, ctypes.c_int]
     lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
-                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)]
     lib.lb_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.lb_step_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.c_int]
@@ -181,12 +182,14 @@ def lb_sweep(h, which: int):
 
 def lb_layout(h):
     """(population byte offset, moment byte offset, block size B in nodes,
-    padded node count): element (a, n) of a region of NA arrays sits at
-    element (n // B) * NA * B + a * B + n % B of that region."""
-    a, b, c, d = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load().lb_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
-           "lb_layout")
-    return a.value, b.value, c.value, d.value
+    padded storage node count, row pitch px): node (x, y, z) is storage node
+    n = x + px (y + ny z), and element (a, n) of a region of NA arrays sits
+    at element (n // B) * NA * B + a * B + n % B of that region."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    c, d, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().lb_layout(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                            ctypes.byref(e)), "lb_layout")
+    return a.value, b.value, c.value, d.value, e.value
 
 
 def lb_synchronize(h):

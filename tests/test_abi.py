@@ -119,34 +119,52 @@ def test_strerror_and_null_destroy():
     assert lb.load().lb_copy(None, None, 16, None) == lb.LB_EINVAL
 
 
-def _blocked_bytes(Q, M, N, ssize, csize, species=1):
-    """Footprint of the documented blocked layout: block B = 32 KiB of
-    population storage (at least 1024 nodes, at most the next power of two
-    >= N), node count padded to a multiple of B, each region 256-byte
-    aligned, plus 64 KiB of FP64 reduction partials."""
+def _blocked_bytes(Q, M, NS, ssize, csize, species=1):
+    """Footprint of the documented blocked layout over NS storage nodes:
+    block B = 32 KiB of population storage (at least 1024 nodes, at most the
+    next power of two >= NS), node count padded to a multiple of B, each
+    region 256-byte aligned, plus 64 KiB of FP64 reduction partials."""
     B = 1024
-    while B < N and B * ssize < 32768:
+    while B < NS and B * ssize < 32768:
         B *= 2
-    npad = -(-N // B) * B
+    npad = -(-NS // B) * B
     al = lambda v: -(-v // 256) * 256
     return al(species * Q * npad * ssize) + al(M * npad * csize) + al(1024 * 8 * 8), B, npad
 
 
 def test_required_bytes_of_ragged_domains():
+    """Storage nodes = px ny nz with the row pitch px: nx rounded up to the
+    stream-collide sweep's vector chunk, where the sweep takes the narrowest
+    lane vector V that needs no more 64-lane wavefronts per row than its
+    widest one (D3Q19 FP32: V <= 4 in chunks of 2; 16-bit D3Q19 / D2Q9:
+    V <= 8 in one chunk; D3Q27 FP32: V <= 4 in one chunk; two species FP32:
+    V <= 4, FP64: V <= 2)."""
+    f16, f64 = lb.LB_STORE_F16S, lb.LB_STORE_F64
     cases = [
-        (dict(lattice=19, nx=37, ny=5, nz=7), 19, 10, 4, 4, 1),
-        (dict(lattice=19, nx=100, ny=90, nz=3), 19, 10, 4, 4, 1),
-        (dict(lattice=9, nx=300, ny=70, nz=1, storage=lb.LB_STORE_F16S), 9, 6, 2, 4, 1),
-        (dict(lattice=27, nx=20, ny=19, nz=18, hermite_order=3, storage=lb.LB_STORE_F64,
-              compute=lb.LB_COMPUTE_F64), 27, 10, 8, 8, 1),
-        (dict(lattice=19, nx=24, ny=20, nz=18, species=2, sigma=0.03, beta=0.7), 19, 11, 4, 4, 2),
-        (dict(lattice=19, nx=1, ny=1, nz=1), 19, 10, 4, 4, 1),
+        # (params, Q, M, storage bytes, compute bytes, species, row pitch)
+        (dict(lattice=19, nx=37, ny=5, nz=7), 19, 10, 4, 4, 1, 37),       # V = 1
+        (dict(lattice=19, nx=100, ny=90, nz=3), 19, 10, 4, 4, 1, 100),    # V = 2
+        (dict(lattice=9, nx=300, ny=70, nz=1, storage=f16), 9, 6, 2, 4, 1, 304),  # V = 8
+        (dict(lattice=27, nx=20, ny=19, nz=18, hermite_order=3, storage=f64,
+              compute=lb.LB_COMPUTE_F64), 27, 10, 8, 8, 1, 20),
+        (dict(lattice=19, nx=24, ny=20, nz=18, species=2, sigma=0.03, beta=0.7), 19, 11, 4, 4, 2,
+         24),
+        (dict(lattice=19, nx=1, ny=1, nz=1), 19, 10, 4, 4, 1, 1),
+        (dict(lattice=19, nx=97, ny=6, nz=5), 19, 10, 4, 4, 1, 98),       # V = 2
+        (dict(lattice=19, nx=131, ny=5, nz=4), 19, 10, 4, 4, 1, 132),     # V = 4 = 2 x 2
+        (dict(lattice=19, nx=161, ny=4, nz=3, storage=f16), 19, 10, 2, 4, 1, 164),  # V = 4
+        (dict(lattice=27, nx=197, ny=4, nz=3, hermite_order=3), 27, 10, 4, 4, 1, 200),
+        (dict(lattice=19, nx=197, ny=6, nz=5, species=2, sigma=0.03, beta=0.7), 19, 11, 4, 4, 2,
+         200),
+        (dict(lattice=19, nx=131, ny=6, nz=5, species=2, sigma=0.03, beta=0.7, storage=f64,
+              compute=lb.LB_COMPUTE_F64), 19, 11, 8, 8, 2, 132),
+        (dict(lattice=19, nx=511, ny=3, nz=2), 19, 10, 4, 4, 1, 512),     # V = 4
+        (dict(lattice=19, nx=64, ny=3, nz=2, storage=f16), 19, 10, 2, 4, 1, 64),   # V = 1
     ]
-    for kw, Q, M, ss, cs, sp in cases:
+    for kw, Q, M, ss, cs, sp, px in cases:
         p = lb.lb_params_default(**kw)
-        N = p.nx * p.ny * p.nz
-        want, B, npad = _blocked_bytes(Q, M, N, ss, cs, sp)
-        assert lb.lb_required_bytes(p) == want, (kw, B, npad)
+        want, B, npad = _blocked_bytes(Q, M, px * p.ny * p.nz, ss, cs, sp)
+        assert lb.lb_required_bytes(p) == want, (kw, px, B, npad)
 
 
 def test_wall_velocity_validation():

@@ -1,7 +1,8 @@
 """The device layout that lb_layout documents (blocked structure of arrays).
 
-The raw population region, decoded with the documented formula
-(element (a, n) of a region of NA arrays at (n // B) NA B + a B + n % B),
+The raw population region, decoded with the documented formula (node
+(x, y, z) at storage node n = x + px (y + ny z), element (a, n) of a region
+of NA arrays at (n // B) NA B + a B + n % B),
 must hold at every node the oracle's equilibrium populations of the
 initial fields (stored shifted, f_a - t_a rho0); the population ordering is
 internal, so each node's values are compared as a multiset.  The moment
@@ -18,18 +19,24 @@ pytestmark = pytest.mark.gpu
 
 NP = {"f32": np.float32, "f16s": np.float16, "f64": np.float64}
 # (lattice, shape, storage, species): one block, several blocks with a
-# ragged tail, 16-bit blocks, FP64 blocks, and the two-species 2Q region
+# ragged tail, 16-bit blocks with padded rows, FP64 blocks, the two-species
+# 2Q region, and padded rows of FP32 and two species
 CASES = [
     (19, (37, 5, 7), "f32", 1),
     (19, (100, 90, 3), "f32", 1),
     (9, (300, 70, 1), "f16s", 1),
     (27, (20, 19, 18), "f64", 1),
     (19, (24, 20, 18), "f32", 2),
+    (19, (97, 30, 5), "f32", 1),
+    (19, (99, 12, 10), "f32", 2),
 ]
 
 
-def _decode(region, NA, B, N):
+def _decode(region, NA, B, shape, px):
+    nx = shape[0]
+    N = shape[0] * shape[1] * shape[2]
     n = np.arange(N)
+    n = n % nx + (n // nx) * px  # storage node
     idx = (n // B)[None, :] * (NA * B) + np.arange(NA)[:, None] * B + (n % B)[None, :]
     return region[idx]
 
@@ -45,8 +52,9 @@ def test_population_layout_matches_documentation(case):
     phi = np.where(np.random.default_rng(case).uniform(size=N) > 0.5, 1.0, -1.0) if species == 2 else None
     sim.init(rho, u, phi)
     sim.synchronize()
-    pop_off, mom_off, B, npad = lb.lb_layout(sim.handle)
-    assert B & (B - 1) == 0 and B >= 1024 and npad % B == 0 and npad >= N
+    pop_off, mom_off, B, npad, px = lb.lb_layout(sim.handle)
+    assert B & (B - 1) == 0 and B >= 1024 and npad % B == 0 and npad >= px * N // shape[0]
+    assert shape[0] <= px < shape[0] + 8
     raw = sim.buffer.cpu().numpy()
     sim.close()
 
@@ -56,7 +64,7 @@ def test_population_layout_matches_documentation(case):
                        sigma=kw.get("sigma", 0.0), beta=kw.get("beta", 0.0))
     fe = oracle.init(op, rho, u, phi).reshape(species * Q, N)
     pops = raw[pop_off:pop_off + species * Q * npad * np.dtype(NP[storage]).itemsize]
-    got = _decode(pops.view(NP[storage]).astype(np.float64), species * Q, B, N)
+    got = _decode(pops.view(NP[storage]).astype(np.float64), species * Q, B, shape, px)
     if species == 1:
         sets = [(got, fe - w[:, None] * 1.0)]
     else:
@@ -76,11 +84,12 @@ def test_moment_layout_after_moments_sweep():
     sim.init(rho, u)
     lb.lb_sweep(sim.handle, 0)
     sim.synchronize()
-    pop_off, mom_off, B, npad = lb.lb_layout(sim.handle)
+    pop_off, mom_off, B, npad, px = lb.lb_layout(sim.handle)
     raw = sim.buffer.cpu().numpy()
     sim.close()
     M = 10
-    mom = _decode(raw[mom_off:mom_off + M * npad * 4].view(np.float32).astype(np.float64), M, B, N)
+    mom = _decode(raw[mom_off:mom_off + M * npad * 4].view(np.float32).astype(np.float64), M, B,
+                  (100, 90, 3), px)
     # drho, then j = rho0 u (no force)
     assert np.abs(mom[0] - (rho - 1.0)).max() < 1e-7
     for al in range(3):

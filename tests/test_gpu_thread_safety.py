@@ -40,7 +40,7 @@ def _setup(case, storage="f32"):
 def _views(sim):
     import torch
 
-    pop_off, mom_off, _, _ = lb.lb_layout(sim.handle)
+    pop_off, mom_off, _, _, _ = lb.lb_layout(sim.handle)
     buf = sim.buffer
     esz = 4 if sim.params.storage == lb.LB_STORE_F32 else 8
     pops = buf[pop_off:mom_off]
