@@ -169,7 +169,8 @@ int lb_sweep(lb_handle* h, int which);
  * compute type: drho, j, Pi^neq [, phi]) at moment_offset.  Node (x, y, z)
  * is storage node n = x + row_pitch * (y + ny * z), row_pitch >= nx (nx
  * rounded up so that the stream-collide sweep's vectors stay aligned; the
- * storage nodes x >= nx of a row are padding and hold zero populations).
+ * storage nodes x >= nx of a row are padding: their populations stay zero
+ * and are never read into a lattice node).
  * Both regions are blocked structures of arrays over padded_nodes storage
  * nodes: with B = block_nodes (a power of two), element (a, n) of a region of
  * NA arrays is element (n / B) * NA * B + a * B + n % B of that region.

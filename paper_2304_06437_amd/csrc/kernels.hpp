@@ -81,7 +81,8 @@ __device__ __forceinline__ int64_t astride(const StepParams<C>& p) {
 
 // Storage node of lattice node n = x + nx (y + ny z).  Rows are px >= nx
 // storage nodes apart, so that every row starts on a vector boundary; nodes
-// x in [nx, px) of a row are padding, never written after creation (zero).
+// x in [nx, px) of a row are padding: zero populations (the stream-collide
+// sweep writes only zeros there), never read into a lattice node.
 template <typename C>
 __device__ __forceinline__ int64_t node_at(const StepParams<C>& p, int64_t n) {
   if (p.px == p.nx) return n;
@@ -370,8 +371,8 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 // nodes (16 bytes per lane for E = 4 floats): whole cache lines per
 // instruction.  Rows are px apart, nx rounded up to a multiple of E, so
 // every vector is aligned; where px > nx the vector holding the row's last
-// node (position tl < E - 1) reads padding moments but stores only its
-// first tl + 1 nodes.
+// node (position tl < E - 1) reads padding moments and stores zeros into
+// the padding populations.
 // -------------------------------------------------------------------------
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
 struct StreamCollide {
@@ -386,6 +387,7 @@ struct StreamCollide {
     bool act[H];      // chunk h starts inside the row
     int tl[H];        // position of the row's last node x = nx - 1 in chunk h, E if absent
     int64_t y, z, rowbase;
+    bool padded;      // rows carry padding (px > nx): wave-uniform
   };
 
   // Emit link A for this lane's nodes.
@@ -427,26 +429,31 @@ struct StreamCollide {
             val[e] = (e > 0) ? link_value<L, ORDER, A, C>(own[h][e > 0 ? e - 1 : 0])
                              : link_value<L, ORDER, A, C>(left[h]);
         } else {
-          // source x + 1; for the last node of a padded row (tl < E - 1) that
-          // is the node after the row end, which right holds
           const C rv = link_value<L, ORDER, A, C>(right[h]);
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            if (e < E - 1) {
-              const C v = link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0]);
-              val[e] = (e == tl) ? rv : v;
-            } else {
-              val[e] = rv;
-            }
+          for (int e = 0; e < E; ++e)
+            val[e] = (e < E - 1) ? link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0]) : rv;
+          if (ln.padded) {
+            // source x + 1 of a padded row's last node (tl < E - 1) is the
+            // node after the row end, which right holds
+#pragma unroll
+            for (int e = 0; e < E - 1; ++e)
+              if (e == tl) val[e] = rv;
           }
         }
         S* dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
         const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);   // source x = -1
         const bool cut_hi = (cx < 0) && p.bbx && (tl < E);    // source x = nx
-        if (!(cut_lo || cut_hi || tl < E - 1)) {
+        if (!(cut_lo || cut_hi)) {
+          if (ln.padded) {
+            // the padding after a row's last node keeps zero populations
+#pragma unroll
+            for (int e = 1; e < E; ++e)
+              if (e > tl) val[e] = C(0);
+          }
           store_pack<S, C, E>(dst, val);
         } else {
-          // row ends: skip the links a wall supplies and the padding
+          // x walls: skip the links the wall supplies, and the padding
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             if (e > tl || (cut_lo && e == 0) || (cut_hi && e == tl)) continue;
@@ -477,14 +484,12 @@ struct StreamCollide {
             bv[e] = link_value_plus<L, ORDER, A, C>(own[h][e], extra);
           }
         }
-        S* dst = f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p);
-        if (tl >= E - 1) {
-          store_pack<S, C, E>(dst, bv);
-        } else {
+        if (ln.padded) {
 #pragma unroll
-          for (int e = 0; e < E; ++e)
-            if (e <= tl) dst[e] = Codec<S, C>::store(bv[e]);
+          for (int e = 1; e < E; ++e)
+            if (e > tl) bv[e] = C(0);
         }
+        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
       }
       if constexpr (cx != 0) {
         if (row_in && p.bbx) {
@@ -537,6 +542,7 @@ struct StreamCollide {
     ln.y = row % p.ny;
     ln.z = row / p.ny;
     ln.rowbase = p.px * row;
+    ln.padded = p.px != p.nx;
     const int64_t x0 = seg * W;
     const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
 #pragma unroll

@@ -301,26 +301,35 @@ struct StreamCollide2 {
           else colour_link<L, A, C>(right, gv[e], rv[e]);
         }
       }
+      const bool padded = p.px != p.nx;  // wave-uniform
       if constexpr (cx < 0 && E > 1) {
-        // the last node of a padded row takes source x + 1 from right
-        C gr, rr;
-        colour_link<L, A, C>(right, gr, rr);
+        if (padded) {
+          // the last node of a padded row takes source x + 1 from right
+          C gr, rr;
+          colour_link<L, A, C>(right, gr, rr);
 #pragma unroll
-        for (int e = 0; e < E - 1; ++e)
-          if (e == tl) {
-            gv[e] = gr;
-            rv[e] = rr;
-          }
+          for (int e = 0; e < E - 1; ++e)
+            if (e == tl) {
+              gv[e] = gr;
+              rv[e] = rr;
+            }
+        }
       }
       // the E nodes from t on lie in one block
       const int64_t t = slot<2 * L::Q>(p, p.px * (ty + p.ny * tz) + xs);
       const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);
       const bool cut_hi = (cx < 0) && p.bbx && (tl < E);
-      if (!(cut_lo || cut_hi || tl < E - 1)) {
+      if (!(cut_lo || cut_hi)) {
+        if (padded) {
+          // the padding after a row's last node keeps zero populations
+#pragma unroll
+          for (int e = 1; e < E; ++e)
+            if (e > tl) gv[e] = rv[e] = C(0);
+        }
         store_pack<S, C, E>(fr0 + t, gv);
         store_pack<S, C, E>(fr1 + t, rv);
       } else {
-        // row ends: skip the links a wall supplies and the padding
+        // x walls: skip the links the wall supplies, and the padding
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           if (e > tl || (cut_lo && e == 0) || (cut_hi && e == tl)) continue;
@@ -333,17 +342,13 @@ struct StreamCollide2 {
 #pragma unroll
       for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], gv[e], rv[e]);
       const int64_t t = slot<2 * L::Q>(p, rowbase + xs);
-      if (tl >= E - 1) {
-        store_pack<S, C, E>(f + t + AB * astride(p), gv);
-        store_pack<S, C, E>(f + t + (L::Q + AB) * astride(p), rv);
-      } else {
+      if (p.px != p.nx) {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (e <= tl) {
-            f[t + e + AB * astride(p)] = Codec<S, C>::store(gv[e]);
-            f[t + e + (L::Q + AB) * astride(p)] = Codec<S, C>::store(rv[e]);
-          }
+        for (int e = 1; e < E; ++e)
+          if (e > tl) gv[e] = rv[e] = C(0);
       }
+      store_pack<S, C, E>(f + t + AB * astride(p), gv);
+      store_pack<S, C, E>(f + t + (L::Q + AB) * astride(p), rv);
     }
     if constexpr (cx != 0) {
       if (row_in && p.bbx) {

@@ -204,3 +204,40 @@ def test_padding_never_reaches_lattice_nodes(name):
     for k in clean:
         assert np.array_equal(clean[k], dirty[k]), k
     assert np.all(np.isfinite(dirty["conserved"]))
+
+
+@pytest.mark.parametrize("name", ["d3q19_f32_periodic_97", "d3q19_f32_moving_xwalls_195",
+                                  "d3q19_f16s_161", "two_species_f32_99"])
+def test_padding_populations_stay_zero(name):
+    """The sweep stores whole vectors at a padded row end, with zeros for the
+    padding: after stepping, every padding population is exactly zero."""
+    import torch
+
+    if name in CASES:
+        lattice, shape, storage, _, kw, _ = CASES[name]
+        p = make_params(lattice=lattice, shape=shape, storage=storage, **kw)
+        rho, u = _fields(lattice, shape, seed=15)
+        phi = None
+    elif name in CASES_16:
+        lattice, shape, storage, _, kw, _ = CASES_16[name]
+        p = make_params(lattice=lattice, shape=shape, storage=storage, **kw)
+        rho, u = _fields(lattice, shape, seed=15)
+        phi = None
+    else:
+        shape, storage, _, kw, _ = CASES_2[name]
+        p = make_params(lattice=19, shape=shape, storage=storage, species=2, sigma=0.03,
+                        beta=0.7, tau=1.0, **kw)
+        rho, u, phi = _droplet(shape, seed=15)
+    with Simulation(p) as sim:
+        sim.init(rho, u, phi)
+        sim.step(25)
+        sim.synchronize()
+        pop_off, _, B, npad, px = lb.lb_layout(sim.handle)
+        NA = p.lattice * p.species
+        esz = 4 if storage == "f32" else 2
+        raw = sim.buffer[pop_off:pop_off + NA * npad * esz].cpu().numpy()
+    vals = raw.view(np.float32 if storage == "f32" else np.uint16)
+    nx, rows = shape[0], shape[1] * shape[2]
+    n = (np.arange(rows)[:, None] * px + np.arange(nx, px)[None, :]).reshape(-1)
+    idx = (n // B)[None, :] * (NA * B) + np.arange(NA)[:, None] * B + (n % B)[None, :]
+    assert np.all(vals[idx] == 0)
