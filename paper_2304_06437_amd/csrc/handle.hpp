@@ -123,9 +123,15 @@ struct ImplT {
     constexpr int HH = V / E;
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH, FD>),
-                       dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, h->stream,
-                       (const C*)h->m, (S*)h->f, p);
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    // the instruction-bound FD sweeps get a variant without the padded-row
+    // selects for aligned rows; elsewhere the selects cost no measurable time
+    if (FD && p.px == p.nx)
+      hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH, FD, !FD>), grid, dim3(256), 0,
+                         h->stream, (const C*)h->m, (S*)h->f, p);
+    else
+      hipLaunchKernelGGL((k_stream_collide<L, ORDER, S, C, E, HH, FD, true>), grid, dim3(256), 0,
+                         h->stream, (const C*)h->m, (S*)h->f, p);
     return hipGetLastError();
   }
   static hipError_t stream_collide(const lb_handle* h) {
@@ -322,5 +328,6 @@ inline const Impl* impl2_for_storage(int storage) {
 const Impl* impl_d2q9(int storage, int species);
 const Impl* impl_d3q19(int storage, int species);
 const Impl* impl_d3q27(int order, int storage);
+const Impl* impl_d3q27_order3(int storage);
 
 }  // namespace lbk

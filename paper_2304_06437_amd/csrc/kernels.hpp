@@ -372,9 +372,11 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 // instruction.  Rows are px apart, nx rounded up to a multiple of E, so
 // every vector is aligned; where px > nx the vector holding the row's last
 // node (position tl < E - 1) reads padding moments and stores zeros into
-// the padding populations.
+// the padding populations.  PAD selects that handling at compile time: the
+// PAD = false variant (fewer instructions per link) requires px == nx.
 // -------------------------------------------------------------------------
-template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
+template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false,
+          bool PAD = true>
 struct StreamCollide {
   using ML = MomentLayout<L>;
   using CL = CoefLayout<L, ORDER>;
@@ -387,7 +389,6 @@ struct StreamCollide {
     bool act[H];      // chunk h starts inside the row
     int tl[H];        // position of the row's last node x = nx - 1 in chunk h, E if absent
     int64_t y, z, rowbase;
-    bool padded;      // rows carry padding (px > nx): wave-uniform
   };
 
   // Emit link A for this lane's nodes.
@@ -433,7 +434,7 @@ struct StreamCollide {
 #pragma unroll
           for (int e = 0; e < E; ++e)
             val[e] = (e < E - 1) ? link_value<L, ORDER, A, C>(own[h][e < E - 1 ? e + 1 : 0]) : rv;
-          if (ln.padded) {
+          if constexpr (PAD) {
             // source x + 1 of a padded row's last node (tl < E - 1) is the
             // node after the row end, which right holds
 #pragma unroll
@@ -445,7 +446,7 @@ struct StreamCollide {
         const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);   // source x = -1
         const bool cut_hi = (cx < 0) && p.bbx && (tl < E);    // source x = nx
         if (!(cut_lo || cut_hi)) {
-          if (ln.padded) {
+          if constexpr (PAD) {
             // the padding after a row's last node keeps zero populations
 #pragma unroll
             for (int e = 1; e < E; ++e)
@@ -484,7 +485,7 @@ struct StreamCollide {
             bv[e] = link_value_plus<L, ORDER, A, C>(own[h][e], extra);
           }
         }
-        if (ln.padded) {
+        if constexpr (PAD) {
 #pragma unroll
           for (int e = 1; e < E; ++e)
             if (e > tl) bv[e] = C(0);
@@ -542,7 +543,6 @@ struct StreamCollide {
     ln.y = row % p.ny;
     ln.z = row / p.ny;
     ln.rowbase = p.px * row;
-    ln.padded = p.px != p.nx;
     const int64_t x0 = seg * W;
     const int64_t xend = (x0 + W < p.nx) ? x0 + W : p.nx;
 #pragma unroll
@@ -628,10 +628,11 @@ struct StreamCollide {
   }
 };
 
-template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false>
+template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false,
+          bool PAD = true>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  StreamCollide<L, ORDER, S, C, E, H, FD>::run_wave(
+  StreamCollide<L, ORDER, S, C, E, H, FD, PAD>::run_wave(
       m, f, p, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 

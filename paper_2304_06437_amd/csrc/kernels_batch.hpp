@@ -52,7 +52,9 @@ __global__ __launch_bounds__(256) void k_stream_collide_batch(const JobDesc<C>* 
   if (w >= total) return;  // wave-uniform
   const JobDesc<C>& J = jobs[job_of(jobs, njobs, w)];
   if constexpr (SPECIES == 1)
-    StreamCollide<L, ORDER, S, C, E, H, FD>::run_wave((const C*)J.m, (S*)J.f, J.p, w - J.start);
+    // the padded-row variant: jobs with and without padded rows share a launch
+    StreamCollide<L, ORDER, S, C, E, H, FD, true>::run_wave((const C*)J.m, (S*)J.f, J.p,
+                                                            w - J.start);
   else
     StreamCollide2<L, S, C, E>::run_wave((const C*)J.m, (S*)J.f, J.p, J.cp, w - J.start);
 }
