@@ -131,22 +131,24 @@ def cpu_baseline(workload: str = "d3q19_tg", seconds_hint: float = 15.0):
     }
 
 
-def serving(torch, jobs: int, rate: float, budget_gb: float):
+def serving(torch, jobs: int, rate: float, budget_gb: float, overlap: bool = True):
     """Continuous batching of a seeded Poisson request stream: D2Q9/D3Q19,
     Taylor-Green or channel, FP32 or shifted-FP16 storage, edge
     log-uniform 64..256 (n^2 or n^3), 200-2000 steps, admitted by an HBM
-    budget.  Time-to-solution = arrival to moments on the host."""
+    budget.  Time-to-solution = arrival to moments on the host.  Set-up and
+    read-back overlap the batch's steps (worker thread, own stream)."""
     from paper_2304_06437_amd.serving import GpuBackend, Server, poisson_mix
 
     specs = poisson_mix(jobs, rate=rate, seed=2026)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         be = GpuBackend()
-        rep = Server(be, hbm_budget=int(budget_gb * 1e9), chunk_steps=200).run(specs)
+        rep = Server(be, hbm_budget=int(budget_gb * 1e9), chunk_steps=200,
+                     overlap=overlap).run(specs)
         be.close()
     torch.cuda.synchronize()
     s = rep.summary()
-    s.update({"rate_per_s": rate, "budget_GB": budget_gb,
+    s.update({"rate_per_s": rate, "budget_GB": budget_gb, "overlap": overlap,
               "mix": "D2Q9/D3Q19 x TG/channel x f32/f16s, edge 64..256 log-uniform, "
                      "200-2000 steps, seeded Poisson arrivals"})
     return s
@@ -251,6 +253,8 @@ def main():
                     help="mean arrivals per second, comma-separated: the first is reported as "
                          "'serving' (saturating load), the second as 'serving_below_saturation'")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-serial", action="store_true",
+                    help="serving loop without set-up / read-back overlap")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -359,7 +363,8 @@ def main():
     if args.serve_jobs > 0:
         rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
         for key, rate in zip(("serving", "serving_below_saturation"), rates):
-            out[key] = serving(torch, args.serve_jobs, rate, args.serve_budget_gb)
+            out[key] = serving(torch, args.serve_jobs, rate, args.serve_budget_gb,
+                               overlap=not args.serve_serial)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

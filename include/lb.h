@@ -183,6 +183,15 @@ int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
 /* Wait for all work enqueued on the handle's stream. */
 int lb_synchronize(lb_handle* h);
 
+/* Rebind the handle to another stream (hipStream_t, borrowed; NULL = the
+ * null stream): later calls enqueue their work there.  Nothing is
+ * synchronized: work already enqueued on the old stream must be complete,
+ * or ordered before the new stream's next work by the caller (an event),
+ * before the handle is used again.  Lets a caller set a simulation up or
+ * read it back on a stream of its own and step it in a batch on the
+ * batch's stream.  Not while a call on the handle is in progress. */
+int lb_set_stream(lb_handle* h, void* hip_stream);
+
 /* Read the moments of the current populations (blocks until done).
  *   rho[N]      density (rho0 + deviation), or NULL
  *   u[D*N]      velocity u = (j + F/2)/rho0, or NULL

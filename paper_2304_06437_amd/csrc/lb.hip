@@ -393,6 +393,12 @@ int lb_synchronize(lb_handle* h) {
   return launch_status(hipStreamSynchronize(h->stream));
 }
 
+int lb_set_stream(lb_handle* h, void* hip_stream) {
+  if (!h) return LB_EINVAL;
+  h->stream = (hipStream_t)hip_stream;
+  return LB_OK;
+}
+
 int64_t lb_step_count(const lb_handle* h) { return h ? h->steps : -1; }
 
 int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,

@@ -88,6 +88,7 @@ def load():
     lib.lb_init.argtypes = [H, dp, dp, dp]
     lib.lb_step.argtypes = [H, ctypes.c_int64]
     lib.lb_synchronize.argtypes = [H]
+    lib.lb_set_stream.argtypes = [H, ctypes.c_void_p]
     lib.lb_moments.argtypes = [H, dp, dp, dp, dp, dp]
     lib.lb_step_count.argtypes = [H]
     lib.lb_step_count.restype = ctypes.c_int64
@@ -194,6 +195,11 @@ def lb_layout(h):
 
 def lb_synchronize(h):
     _check(load().lb_synchronize(h), "lb_synchronize")
+
+
+def lb_set_stream(h, stream: int):
+    """Rebind handle h to another HIP stream (the caller orders the work)."""
+    _check(load().lb_set_stream(h, ctypes.c_void_p(stream)), "lb_set_stream")
 
 
 def lb_moments(h, p: lb_params, rho=True, u=True, pineq=True, phi=False, conserved=True,

@@ -17,6 +17,13 @@ boundary.  A request whose footprint exceeds the whole budget is rejected; a
 request whose set-up or read-out fails (or whose state became non-finite) is
 marked failed without affecting the others.
 
+With ``overlap=True`` the set-up of admitted requests and the read-back of
+finished ones run on a worker thread while the main thread steps the batch:
+the GPU backend does that work on a stream of its own and hands each
+simulation to the batch's stream (``lb_set_stream``) once it is initialised,
+and back for the read-back, with that stream ordered after the batch's
+stream after every chunk.
+
 Not part of the paper: the serving loop is how this library runs many small
 independent simulations on one GPU.
 """
@@ -150,6 +157,8 @@ class GpuBackend:
         self.lb = lb
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         self.stream = torch.cuda.current_stream(self.device)
+        # set-up and read-back stream of the overlapped server (default priority)
+        self.side = torch.cuda.Stream(self.device)
         self.batch = lb.lb_batch_create(self.stream.cuda_stream)
         lb.lb_batch_set_graphs(self.batch, graphs)
         self.keep_moments = keep_moments
@@ -178,14 +187,42 @@ class GpuBackend:
         sim.init(rho, u)
         return sim
 
+    def create_aside(self, spec: JobSpec, prepared=None):
+        """create() on the side stream (worker thread); lb_init is synchronous,
+        so the simulation is ready for the batch's stream when this returns."""
+        from .sim import Simulation
+
+        with self.torch.cuda.stream(self.side):
+            sim = Simulation(self.params(spec), device=self.device, stream=self.side)
+            rho, u = prepared if prepared is not None else spec.fields()
+            sim.init(rho, u)
+        sim.set_stream(self.stream)
+        return sim
+
     def step(self, handles, nsteps):
         self.lb.lb_batch_step(self.batch, [s.handle for s in handles], nsteps)
+
+    def chunk_done(self):
+        """Order the side stream after everything enqueued on the batch's
+        stream so far.  Called by the main thread between batch steps, when
+        no graph capture is active on the batch's stream: HIP rejects a wait
+        on that stream's work while it is being captured, even for work
+        recorded before the capture began."""
+        self.side.wait_stream(self.stream)
 
     def read(self, sim, spec: JobSpec) -> dict:
         out = sim.moments(rho=self.keep_moments, u=True, pineq=False, allow_nonfinite=True)
         if out["status"] != self.lb.LB_OK or not np.isfinite(out["u"]).all():
             raise FloatingPointError("non-finite state")
         return out
+
+    def read_aside(self, sim, spec: JobSpec) -> dict:
+        """read() on the side stream (worker thread), which chunk_done() has
+        ordered after the simulation's last chunk; the handle stays on the
+        side stream for destroy()."""
+        sim.set_stream(self.side)
+        with self.torch.cuda.stream(self.side):
+            return self.read(sim, spec)
 
     def destroy(self, sim):
         sim.close()
@@ -199,7 +236,7 @@ class GpuBackend:
 class Server:
     def __init__(self, backend, hbm_budget: int, chunk_steps: int = 200,
                  max_active: int = 256, keep_moments: bool = False, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 sleep=time.sleep, overlap: bool = False):
         self.backend = backend
         self.budget = int(hbm_budget)
         self.chunk = int(chunk_steps)
@@ -207,15 +244,169 @@ class Server:
         self.keep_moments = keep_moments
         self.clock = clock
         self.sleep = sleep
+        self.overlap = overlap
 
     def run(self, specs) -> ServeReport:
         prep = getattr(self.backend, "prepare", None)
         pool = ThreadPoolExecutor(max_workers=2) if prep is not None else None
         try:
+            if self.overlap:
+                return self._run_overlapped(specs, pool, prep)
             return self._run(specs, pool, prep)
         finally:
             if pool is not None:
                 pool.shutdown(wait=True, cancel_futures=True)
+
+    def _admit_check(self, spec, results, futures):
+        """(need, None) for a request that may be admitted, (None, result) for
+        one rejected outright."""
+        res = JobResult(spec.job_id, "queued", spec.arrival)
+        try:
+            need = self.backend.required_bytes(spec)
+        except Exception as e:  # invalid request
+            res.status, res.error = "rejected", str(e)
+        else:
+            if need <= self.budget:
+                return need, res
+            res.status, res.error = "rejected", f"needs {need} B > budget {self.budget} B"
+        futures.pop(spec.job_id, None)
+        results[spec.job_id] = res
+        return None, res
+
+    def _run_overlapped(self, specs, pool, prep) -> ServeReport:
+        """As _run, with set-up and read-back on one worker thread while the
+        main thread steps the resident batch.  Memory counts against the
+        budget from admission until the read-back has released it."""
+        from concurrent.futures import FIRST_COMPLETED, wait
+
+        be = self.backend
+        create = getattr(be, "create_aside", be.create)
+        read = getattr(be, "read_aside", be.read)
+        chunk_done = getattr(be, "chunk_done", lambda: None)
+        worker = ThreadPoolExecutor(max_workers=1)
+        pending = deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))
+        queue: deque = deque()
+        active: list = []
+        creating: list = []   # (future, spec, need, result)
+        reading: list = []    # (future, _Active)
+        results = {}
+        futures = {}
+        used = peak = 0
+        max_active = chunks = 0
+        phase = {"create": 0.0, "step": 0.0, "read": 0.0, "idle": 0.0, "wait": 0.0}
+        t0 = self.clock()
+
+        def now():
+            return self.clock() - t0
+
+        def setup_task(spec, fut):
+            tc = self.clock()
+            try:
+                return create(spec, fut.result()) if fut is not None else create(spec)
+            finally:
+                phase["create"] += self.clock() - tc
+
+        def read_task(a):
+            tr = self.clock()
+            try:
+                out = read(a.handle, a.spec)
+            finally:
+                self._release(a)
+                phase["read"] += self.clock() - tr
+            return out
+
+        try:
+            while pending or queue or active or creating or reading:
+                t = now()
+                while pending and pending[0].arrival <= t:
+                    spec = pending.popleft()
+                    queue.append(spec)
+                    if pool is not None:
+                        futures[spec.job_id] = pool.submit(prep, spec)
+                # finished read-backs release their memory
+                still = []
+                for fut, a in reading:
+                    if not fut.done():
+                        still.append((fut, a))
+                        continue
+                    try:
+                        out = fut.result()
+                        a.result.status = "done"
+                        a.result.lattice_updates = a.spec.nodes * a.spec.steps
+                        if self.keep_moments:
+                            a.result.moments = out
+                    except Exception as e:
+                        a.result.status, a.result.error = "failed", repr(e)
+                    a.result.finished = now()
+                    results[a.spec.job_id] = a.result
+                    used -= a.nbytes
+                reading = still
+                # admission in arrival order while the head of the queue fits
+                while queue and len(active) + len(creating) < self.max_active:
+                    need, res = self._admit_check(queue[0], results, futures)
+                    if need is None:
+                        queue.popleft()
+                        continue
+                    if used + need > self.budget:
+                        break
+                    spec = queue.popleft()
+                    res.admitted = now()
+                    used += need
+                    peak = max(peak, used)
+                    creating.append((worker.submit(setup_task, spec, futures.pop(spec.job_id, None)),
+                                     spec, need, res))
+                # set-ups that have finished join the batch
+                still = []
+                for fut, spec, need, res in creating:
+                    if not fut.done():
+                        still.append((fut, spec, need, res))
+                        continue
+                    try:
+                        active.append(_Active(spec, fut.result(), need, res))
+                    except Exception as e:
+                        res.status, res.error, res.finished = "failed", repr(e), now()
+                        results[spec.job_id] = res
+                        used -= need
+                creating = still
+                max_active = max(max_active, len(active))
+                if not active:
+                    if creating or reading:
+                        tw = self.clock()
+                        wait([f for f, *_ in creating] + [f for f, _ in reading],
+                             return_when=FIRST_COMPLETED)
+                        phase["wait"] += self.clock() - tw
+                    elif pending and not queue:
+                        ti = self.clock()
+                        self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                        phase["idle"] += self.clock() - ti
+                    continue
+                nsteps = [min(self.chunk, a.remaining) for a in active]
+                ts = self.clock()
+                try:
+                    be.step([a.handle for a in active], nsteps)
+                    chunk_done()  # read-backs below are ordered after this chunk
+                    phase["step"] += self.clock() - ts
+                except Exception as e:
+                    for a in active:
+                        a.result.status, a.result.error, a.result.finished = "failed", repr(e), now()
+                        results[a.spec.job_id] = a.result
+                        self._release(a)
+                        used -= a.nbytes
+                    active = []
+                    continue
+                chunks += 1
+                still = []
+                for a, k in zip(active, nsteps):
+                    a.remaining -= k
+                    if a.remaining > 0:
+                        still.append(a)
+                    else:
+                        reading.append((worker.submit(read_task, a), a))
+                active = still
+        finally:
+            worker.shutdown(wait=True)
+        ordered = [results[s.job_id] for s in sorted(specs, key=lambda s: s.job_id)]
+        return ServeReport(ordered, now(), max_active, peak, chunks, phase)
 
     def _run(self, specs, pool, prep) -> ServeReport:
         pending = deque(sorted(specs, key=lambda s: (s.arrival, s.job_id)))

@@ -59,6 +59,11 @@ class Simulation:
     def synchronize(self):
         lb.lb_synchronize(self.handle)
 
+    def set_stream(self, stream):
+        """Enqueue later work on another torch stream (the caller orders it)."""
+        lb.lb_set_stream(self.handle, stream.cuda_stream)
+        self.stream = stream
+
     def moments(self, **kw):
         return lb.lb_moments(self.handle, self.params, **kw)
 

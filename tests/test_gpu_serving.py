@@ -107,26 +107,31 @@ def test_batch_rejects_bad_arguments():
     sim.close()
 
 
-def test_serving_loop_end_to_end():
+@pytest.mark.parametrize("overlap", [False, True])
+def test_serving_loop_end_to_end(overlap):
     """Small Poisson stream with a budget that forces queueing: every request
-    completes, and a sample of results equals the request run on its own."""
+    completes, and a sample of results equals the request run on its own
+    (also with set-up and read-back on the worker thread and side stream)."""
     import torch
 
     specs = poisson_mix(24, rate=200.0, seed=11, edge_min=24, edge_max=64, steps=(50, 300))
     with torch.cuda.stream(_stream()):
         be = GpuBackend(keep_moments=True)
         budget = 3 * max(be.required_bytes(s) for s in specs)
-        rep = Server(be, hbm_budget=budget, chunk_steps=64, keep_moments=True).run(specs)
+        rep = Server(be, hbm_budget=budget, chunk_steps=64, keep_moments=True,
+                     overlap=overlap).run(specs)
         be.close()
     summ = rep.summary()
     print(summ)
-    assert summ["done"] == len(specs)
+    failed = [(r.job_id, r.status, r.error) for r in rep.results if r.status != "done"]
+    assert summ["done"] == len(specs), failed
     assert rep.peak_bytes <= budget
     assert np.isfinite(rep.p50) and rep.p99 >= rep.p50
-    for s in specs[:4]:
+    for s in specs:
         alone = _batch_run([s])[0]
         got = rep.results[s.job_id].moments
         assert np.array_equal(got["u"], alone["u"]), s.job_id
+        assert np.array_equal(got["rho"], alone["rho"]), s.job_id
 
 
 def test_one_shot_step_batch_equals_batch_object():

@@ -114,6 +114,93 @@ def test_late_short_request_joins_and_finishes_first():
     assert rep.max_active == 2
 
 
+class ThreadedBackend:
+    """Real-time fake for the overlapped server: set-up and read-back run on
+    the worker thread while steps run on the main thread; tracks the live
+    bytes under a lock and records when set-ups ran during a step."""
+
+    def __init__(self, bytes_per_node=100, fail_create=(), fail_read=(), t_create=0.004,
+                 t_read=0.002, s_per_lu=2e-9):
+        import threading
+
+        self.lock = threading.Lock()
+        self.bpn = bytes_per_node
+        self.fail_create, self.fail_read = set(fail_create), set(fail_read)
+        self.t_create, self.t_read, self.s_per_lu = t_create, t_read, s_per_lu
+        self.live = self.max_live = self.live_bytes = self.max_live_bytes = 0
+        self.admit_order = []
+        self.stepping = False
+        self.overlapped = 0
+
+    def required_bytes(self, spec):
+        return spec.nodes * self.bpn
+
+    def create(self, spec):
+        import time as _t
+
+        with self.lock:
+            self.admit_order.append(spec.job_id)
+            self.overlapped += self.stepping
+        _t.sleep(self.t_create)
+        if spec.job_id in self.fail_create:
+            raise RuntimeError("create failed")
+        with self.lock:
+            self.live += 1
+            self.max_live = max(self.max_live, self.live)
+            self.live_bytes += self.required_bytes(spec)
+            self.max_live_bytes = max(self.max_live_bytes, self.live_bytes)
+        return spec
+
+    def step(self, handles, nsteps):
+        import time as _t
+
+        self.stepping = True
+        _t.sleep(sum(h.nodes * k for h, k in zip(handles, nsteps)) * self.s_per_lu)
+        self.stepping = False
+
+    def read(self, h, spec):
+        import time as _t
+
+        _t.sleep(self.t_read)
+        if spec.job_id in self.fail_read:
+            raise FloatingPointError("non-finite state")
+        return {"job": spec.job_id}
+
+    def destroy(self, h):
+        with self.lock:
+            self.live -= 1
+            self.live_bytes -= self.required_bytes(h)
+
+
+def test_overlapped_server_respects_budget_order_and_failures():
+    be = ThreadedBackend(fail_create={2}, fail_read={5})
+    specs = _specs(10, gap=2e-3)
+    need = specs[0].nodes * 100
+    rep = Server(be, hbm_budget=int(3.5 * need), chunk_steps=40, keep_moments=True,
+                 overlap=True).run(specs)
+    st = [r.status for r in rep.results]
+    assert st == ["done", "done", "failed", "done", "done", "failed", "done", "done", "done", "done"]
+    assert be.admit_order == list(range(10))
+    assert be.max_live_bytes <= 3.5 * need and rep.peak_bytes <= 3.5 * need
+    assert be.live == 0 and be.live_bytes == 0
+    assert all(r.moments == {"job": r.job_id} for r in rep.results if r.status == "done")
+    assert all(r.admitted >= r.arrival and r.finished >= r.admitted for r in rep.results)
+    # set-ups ran on the worker while the main thread was stepping
+    assert be.overlapped > 0
+    assert set(rep.phase_s) >= {"create", "step", "read", "wait", "idle"}
+
+
+def test_overlapped_server_matches_serial_statuses_and_work():
+    specs = poisson_mix(30, rate=400.0, seed=3, edge_min=8, edge_max=24, steps=(20, 120))
+    clk = FakeClock()
+    serial = Server(CountingBackend(clk), hbm_budget=60 * 24 ** 3 * 100, chunk_steps=25,
+                    clock=clk, sleep=clk.sleep).run(specs)
+    over = Server(ThreadedBackend(s_per_lu=1e-10), hbm_budget=60 * 24 ** 3 * 100, chunk_steps=25,
+                  overlap=True).run(specs)
+    assert [r.status for r in over.results] == [r.status for r in serial.results]
+    assert over.lattice_updates == serial.lattice_updates
+
+
 def test_percentiles_and_throughput():
     res = [JobResult(i, "done", 0.0, 0.0, float(i + 1), lattice_updates=10 ** 6) for i in range(100)]
     res.append(JobResult(100, "failed", 0.0, 0.0, 1e9))
