@@ -117,6 +117,7 @@ def test_strerror_and_null_destroy():
     assert lb.load().lb_step(None, 1) == lb.LB_EINVAL
     assert lb.load().lb_moments(None, None, None, None, None, None) == lb.LB_EINVAL
     assert lb.load().lb_copy(None, None, 16, None) == lb.LB_EINVAL
+    assert lb.load().lb_set_stream(None, None) == lb.LB_EINVAL
 
 
 def _blocked_bytes(Q, M, NS, ssize, csize, species=1):
