@@ -242,8 +242,13 @@ struct ImplT2 {
   static hipError_t sc(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    hipLaunchKernelGGL((k_stream_collide2<L, S, C, E>), dim3((unsigned)((waves + 3) / 4)),
-                       dim3(256), 0, h->stream, (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
+    const dim3 grid((unsigned)((waves + 3) / 4));
+    if (p.nseg == 1 && !p.bbx && p.px == p.nx)
+      hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, true>), grid, dim3(256), 0, h->stream,
+                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
+    else
+      hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, false>), grid, dim3(256), 0, h->stream,
+                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
     return hipGetLastError();
   }
   static hipError_t stream_collide(const lb_handle* h) {

@@ -257,8 +257,11 @@ __device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], 
 
 // Stream-collide for two species.  One wavefront per x-row segment of 64 E
 // nodes (E per lane), as in StreamCollide; the phase-field gradient reads
-// phi from the 3 (2D) or 9 (3D) rows around the source row.
-template <class L, typename S, typename C, int E>
+// phi from the 3 (2D) or 9 (3D) rows around the source row.  WHOLE: every
+// row is one periodic, unpadded segment (nseg = 1, no x walls, px = nx), so
+// the states beyond the row's two ends are those of its other end, taken
+// from the lanes that hold them instead of recomputed.
+template <class L, typename S, typename C, int E, bool WHOLE = false>
 struct StreamCollide2 {
   using ML = MomentLayout<L>;
   using XL = ColourLayout<L>;
@@ -536,34 +539,48 @@ struct StreamCollide2 {
       left[q] = lane_from_below(own[E - 1][q]);
       right[q] = lane_from_above(own[0][q]);
     }
-    if (lane == 0) {
-      int64_t xl = x0 - 1;
-      bool ok = true;
-      if (xl < 0) {
-        if (p.bbx) ok = false;
-        else xl = p.nx - 1;
+    if constexpr (WHOLE) {
+      // the whole periodic row is in this wavefront: the neighbours of its
+      // ends are the states of its other end, already in registers (lane lt
+      // holds x = nx - 1 as its last node)
+      const int lt = (int)(p.nx / E) - 1;  // wave-uniform
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const C vl = lane_bcast(own[E - 1][q], lt);
+        const C vr = lane_bcast(own[0][q], 0);
+        if (lane == 0) left[q] = vl;
+        if (lane == lt) right[q] = vr;
       }
-      if (ok) colour_state_scalar<L, C>(m, p, cp, xl, y, z, left);
-    }
-    if (act && xs + E >= xend) {
-      int64_t xr = xend;
-      bool ok = true;
-      if (xr >= p.nx) {
-        if (p.bbx) ok = false;
-        else xr = 0;
+    } else {
+      if (lane == 0) {
+        int64_t xl = x0 - 1;
+        bool ok = true;
+        if (xl < 0) {
+          if (p.bbx) ok = false;
+          else xl = p.nx - 1;
+        }
+        if (ok) colour_state_scalar<L, C>(m, p, cp, xl, y, z, left);
       }
-      if (ok) colour_state_scalar<L, C>(m, p, cp, xr, y, z, right);
+      if (act && xs + E >= xend) {
+        int64_t xr = xend;
+        bool ok = true;
+        if (xr >= p.nx) {
+          if (p.bbx) ok = false;
+          else xr = 0;
+        }
+        if (ok) colour_state_scalar<L, C>(m, p, cp, xr, y, z, right);
+      }
     }
     if (!act) return;
     links<0>(f, p, own, left, right, xs, tl, y, z, rowbase);
   }
 };
 
-template <class L, typename S, typename C, int E>
+template <class L, typename S, typename C, int E, bool WHOLE = false>
 __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m,
                                                          S* __restrict__ f, StepParams<C> p,
                                                          ColourParams<C> cp) {
-  StreamCollide2<L, S, C, E>::run_wave(
+  StreamCollide2<L, S, C, E, WHOLE>::run_wave(
       m, f, p, cp, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
