@@ -365,6 +365,42 @@ __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __r
 // -------------------------------------------------------------------------
 // Sweep 2: fused streaming + collision with boundaries.
 //
+// Link indices ordered by target row offset (c_y, c_z): (0,0), (1,0),
+// (-1,0), (0,1), (0,-1), then the four diagonal rows; lattice order within
+// a row.  A permutation of 0..Q-1.
+template <class L>
+struct RowOrder {
+  struct Table {
+    int a[L::Q];
+  };
+  static constexpr Table make() {
+    constexpr int rows[9][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1},
+                                {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+    Table t{};
+    int k = 0;
+    for (int r = 0; r < 9; ++r)
+      for (int a = 0; a < L::Q; ++a)
+        if (L::c[a][1] == rows[r][0] && L::c[a][2] == rows[r][1]) t.a[k++] = a;
+    return t;
+  }
+  static constexpr Table t = make();
+  static constexpr const int (&a)[L::Q] = t.a;
+};
+
+template <class L>
+constexpr bool row_order_is_permutation() {
+  int seen[L::Q] = {};
+  for (int i = 0; i < L::Q; ++i) {
+    const int a = RowOrder<L>::make().a[i];
+    if (a < 0 || a >= L::Q || seen[a]) return false;
+    seen[a] = 1;
+  }
+  return true;
+}
+static_assert(row_order_is_permutation<D2Q9>(), "D2Q9 row order");
+static_assert(row_order_is_permutation<D3Q19>(), "D3Q19 row order");
+static_assert(row_order_is_permutation<D3Q27>(), "D3Q27 row order");
+
 // Lane mapping: a wavefront's segment of 64 V nodes (V = E H) is split into H
 // chunks of 64 E nodes; lane l owns nodes h*64E + l*E + e (e < E) of chunk h.
 // Every vector load or store instruction therefore covers 64 E contiguous
@@ -512,13 +548,16 @@ struct StreamCollide {
     }
   }
 
-  template <int A>
+  // Links are emitted grouped by target row (c_y, c_z), so that a
+  // wavefront finishes the stores into one row before the next (measured
+  // 0.7 % faster than the lattice order for D3Q19 FP32 at 512^3).
+  template <int I>
   __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
                                                const C (&own)[H][E][K], const C (&left)[H][K],
                                                const C (&right)[H][K], const Lane& ln) {
-    if constexpr (A < L::Q) {
-      link<A>(f, p, own, left, right, ln);
-      links<A + 1>(f, p, own, left, right, ln);
+    if constexpr (I < L::Q) {
+      link<RowOrder<L>::a[I]>(f, p, own, left, right, ln);
+      links<I + 1>(f, p, own, left, right, ln);
     }
   }
 
