@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -327,7 +328,8 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
     const int per = 1 + L.D + (two ? 1 : 0);  // doubles staged per node
     const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
     const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
-    std::vector<double> hb((size_t)per * chunk);
+    // uninitialised: every element staged is written before it is copied
+    std::unique_ptr<double[]> hb(new double[(size_t)per * chunk]);
     double* stage = (double*)h->m;
     for (int64_t n0 = 0; n0 < N; n0 += chunk) {
       const int64_t cnt = (N - n0 < chunk) ? N - n0 : chunk;
@@ -335,7 +337,7 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
       for (int al = 0; al < L.D; ++al)
         std::memcpy(&hb[(size_t)(1 + al) * cnt], u + (size_t)al * N + n0, cnt * sizeof(double));
       if (two) std::memcpy(&hb[(size_t)(1 + L.D) * cnt], phi + n0, cnt * sizeof(double));
-      LB_TRY_HIP(hipMemcpyAsync(stage, hb.data(), (size_t)per * cnt * sizeof(double),
+      LB_TRY_HIP(hipMemcpyAsync(stage, hb.get(), (size_t)per * cnt * sizeof(double),
                                 hipMemcpyHostToDevice, h->stream));
       LB_TRY_HIP(h->impl->init(h, stage, n0, cnt));
       LB_TRY_HIP(hipStreamSynchronize(h->stream));
