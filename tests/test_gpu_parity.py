@@ -289,3 +289,37 @@ def test_maximum_size_node_index_beyond_2_31():
         assert abs(got["rho"][nidx] - ref["rho"][c]) < 1e-7
     print(f"{nx}x{ny} ({nx * ny} nodes) sampled: max |du|/u0 = {worst:.3e}")
     assert worst <= FP32_TOL
+
+
+@pytest.mark.timeout(300)
+def test_maximum_size_with_padded_rows():
+    """The same size class with an odd row length: 46401 x 46300 = 2.148e9
+    nodes, stored with row pitch 46402 (two-node lane chunks), so the storage
+    index of a lattice node passes 2^31 through the pitch arithmetic and
+    every row ends inside a vector.  Sampled nodes at row ends and starts,
+    in the last rows and at the last node match the oracle on their
+    dependency cones after 6 steps."""
+    import torch
+
+    torch.cuda.empty_cache()  # the previous test's 129 GB block
+    nx, ny, steps, tau, u0 = 46401, 46300, 6, 0.8, 0.01
+    assert nx * ny > 2**31
+    rho, u = inputs.taylor_green_2d(nx, ny, u0)
+    p = make_params(lattice=9, shape=(nx, ny, 1), tau=tau)
+    got = run(p, rho, u, steps, pineq=False, conserved=False)
+    h = steps + 2
+    off = np.arange(-h, h + 1)
+    samples = [(0, 0), (nx - 1, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 2, 40000),
+               (nx - 1, 30001), (1, 30001), (23200, 46282), (nx - 1, 46282)]
+    worst = 0.0
+    for (x, y) in samples:
+        ix, iy = (x + off) % nx, (y + off) % ny
+        sub = (iy[:, None] * nx + ix[None, :]).reshape(-1)
+        q = oracle.Params(lattice=9, nx=2 * h + 1, ny=2 * h + 1, nz=1, tau=tau)
+        ref = oracle.simulate(q, rho[sub], u[:, sub], steps)
+        c = h + (2 * h + 1) * h
+        nidx = x + nx * y
+        worst = max(worst, np.abs(got["u"][:, nidx] - ref["u"][:, c]).max() / u0)
+        assert abs(got["rho"][nidx] - ref["rho"][c]) < 1e-7
+    print(f"{nx}x{ny} ({nx * ny} nodes, padded rows) sampled: max |du|/u0 = {worst:.3e}")
+    assert worst <= FP32_TOL
