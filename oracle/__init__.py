@@ -62,6 +62,10 @@ class _Params(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("beta", ctypes.c_double),
         ("wall_u", ctypes.c_double * 18),
+        ("nci_strength", ctypes.c_double),
+        ("nci_eps", ctypes.c_double),
+        ("nci_reach", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -81,6 +85,9 @@ class Params:
     sigma: float = 0.0
     beta: float = 0.0
     wall_u: tuple = None         # [axis][low, high][component] wall velocities
+    nci_strength: float = 0.0    # near-contact force constant (two species); 0 = off
+    nci_eps: float = 0.1         # bulk threshold: phi < -1 + nci_eps
+    nci_reach: int = 1           # sampling distance along lattice directions
 
     @property
     def D(self) -> int:
@@ -107,6 +114,9 @@ class Params:
             wu = np.asarray(self.wall_u, dtype=np.float64).reshape(18)
             for i in range(18):
                 p.wall_u[i] = float(wu[i])
+        p.nci_strength = self.nci_strength
+        p.nci_eps = self.nci_eps
+        p.nci_reach = self.nci_reach
         return p
 
 
@@ -127,6 +137,7 @@ def _load():
         lib.ref_collide_node.argtypes = [pp, dp, dp]
         lib.ref_equilibrium_node.argtypes = [pp, ctypes.c_double, dp, dp]
         lib.ref_threads.argtypes = []
+        lib.ref_nci.argtypes = [pp, dp, ctypes.POINTER(ctypes.c_uint8), dp]
         _lib = lib
     return _lib
 
@@ -233,3 +244,17 @@ def equilibrium_node(p: Params, rho: float, u) -> np.ndarray:
     if lib.ref_equilibrium_node(ctypes.byref(pc), float(rho), _ptr(uu), _ptr(out)) != 0:
         raise ValueError("invalid parameters")
     return out
+
+
+def nci(p: Params, f: np.ndarray):
+    """Near-contact flags[N] (bool) and forces[D, N] of the current
+    two-species populations (Section 2.2, flagging pass and force)."""
+    lib = _load()
+    N = p.N
+    flag = np.zeros(N, dtype=np.uint8)
+    force = np.empty(3 * N)
+    pc = p._c()
+    if lib.ref_nci(ctypes.byref(pc), _ptr(f), flag.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                   _ptr(force)) != 0:
+        raise ValueError("invalid parameters")
+    return flag.astype(bool), force.reshape(3, N)[: p.D]

@@ -51,7 +51,8 @@
  *   does not print the weights).
  *
  *   Two-species colour-gradient collision (Section 2.1) is in
- *   step_two_species below.
+ *   step_two_species below, with the near-contact interactions of Section
+ *   2.2 (nci_flags, nci_force).
  *
  * Compiled with -ffp-contract=off so that every node performs bit-identical
  * arithmetic (translation equivariance is a test).
@@ -81,6 +82,10 @@ typedef struct {
   double beta;      /* recolouring (anti-diffusion) parameter */
   double wall_u[3][2][3]; /* velocity of the wall at [axis][low, high]: tangential,
                              bounce-back axes only, one species only */
+  double nci_strength;    /* near-contact force constant A (two species); 0 = off */
+  double nci_eps;         /* bulk threshold: a node is bulk if phi < -1 + eps */
+  int32_t nci_reach;      /* sampling distance d along a lattice direction (>= 1) */
+  int32_t pad_;
 } ref_params;
 
 typedef struct {
@@ -184,9 +189,9 @@ static void equilibrium(const lattice_t* L, const ref_params* p, double rho, con
 }
 
 /* Moments of one node: rho, j, and the velocity of the forced incompressible
- * model u = (j + F/2)/rho0. */
-static void node_moments(const lattice_t* L, const ref_params* p, const double* f, double* rho,
-                         double j[3], double u[3]) {
+ * model u = (j + F/2)/rho0 for the body force F acting on the node. */
+static void node_moments_f(const lattice_t* L, const ref_params* p, const double* f,
+                           const double F[3], double* rho, double j[3], double u[3]) {
   double r = 0.0;
   j[0] = j[1] = j[2] = 0.0;
   for (int a = 0; a < L->q; ++a) {
@@ -194,16 +199,22 @@ static void node_moments(const lattice_t* L, const ref_params* p, const double* 
     for (int al = 0; al < 3; ++al) j[al] += f[a] * L->c[a][al];
   }
   *rho = r;
-  for (int al = 0; al < 3; ++al) u[al] = (j[al] + 0.5 * p->force[al]) / p->rho0;
+  for (int al = 0; al < 3; ++al) u[al] = (j[al] + 0.5 * F[al]) / p->rho0;
 }
 
-/* Regularized collision of one node: f (Q values) -> f^pc (Q values).
- * Steps 1-4 of the header. */
-static void collide(const lattice_t* L, const ref_params* p, const double* f, double* fpc) {
+static void node_moments(const lattice_t* L, const ref_params* p, const double* f, double* rho,
+                         double j[3], double u[3]) {
+  node_moments_f(L, p, f, p->force, rho, j, u);
+}
+
+/* Regularized collision of one node under the body force F: f (Q values) ->
+ * f^pc (Q values).  Steps 1-4 of the header. */
+static void collide_f(const lattice_t* L, const ref_params* p, const double* f,
+                      const double F[3], double* fpc) {
   const int Q = L->q;
   const double omega = 1.0 / p->tau;
   double rho, j[3], u[3];
-  node_moments(L, p, f, &rho, j, u);
+  node_moments_f(L, p, f, F, &rho, j, u);
 
   double feq[27], fneq[27];
   equilibrium(L, p, rho, u, feq);
@@ -222,7 +233,6 @@ static void collide(const lattice_t* L, const ref_params* p, const double* f, do
       for (int ga = 0; ga < 3; ++ga)
         a3[al][be][ga] = u[al] * Pi[be][ga] + u[be] * Pi[al][ga] + u[ga] * Pi[al][be];
 
-  const double* F = p->force;
   for (int a = 0; a < Q; ++a) {
     double fhat = cdot(L, a, a1) / CS2 + h2dot(L, a, Pi) / (2.0 * CS4);
     if (p->order >= 3) fhat += h3dot(L, a, a3) / (6.0 * CS6);
@@ -233,6 +243,11 @@ static void collide(const lattice_t* L, const ref_params* p, const double* f, do
     double S = L->w[a] * (cmuF / CS2 + cdot(L, a, u) * cdot(L, a, F) / CS4);
     fpc[a] = feq[a] + (1.0 - omega) * fhat + (1.0 - 0.5 * omega) * S;
   }
+}
+
+/* Collision under the problem's constant body force. */
+static void collide(const lattice_t* L, const ref_params* p, const double* f, double* fpc) {
+  collide_f(L, p, f, p->force, fpc);
 }
 
 /* Destination of population a leaving node (x,y,z).  Returns 1 and the linear
@@ -259,6 +274,8 @@ static int check_params(const ref_params* p, lattice_t* L) {
   if (!(p->tau > 0.5)) return -1;
   if (p->order != 2 && p->order != 3) return -1;
   if (p->species != 1 && p->species != 2) return -1;
+  if (p->nci_strength != 0.0 && (p->species != 2 || p->nci_reach < 1 || !(p->nci_eps > 0.0)))
+    return -1;
   /* wall velocities: tangential, on bounce-back axes, one species */
   for (int al = 0; al < 3; ++al)
     for (int side = 0; side < 2; ++side)
@@ -358,6 +375,64 @@ static void gradient(const lattice_t* L, const ref_params* p, const double* phi,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Near-contact interactions (Section 2.2).                                   */
+/*                                                                            */
+/*   Flagging pass, before the collision, in the paper's scatter form:       */
+/*   sitting on a bulk node x of the continuous phase, phi(x) < -1 + eps,     */
+/*   sample phi at the two points x + d c_a and x - d c_a of every pair of    */
+/*   opposite lattice directions (d = nci_reach).  When neither point is      */
+/*   bulk (both phi > -1 + eps), an interface lies on each side of x along    */
+/*   c_a, and both points are flagged.  A point beyond a bounce-back wall is  */
+/*   not sampled; periodic axes wrap.                                         */
+/*   Force: a flagged node y whose phase gradient G is defined (|G|^2 >      */
+/*   1e-20) carries F_nci(y) = A rho_R(y) G/|G|, along the interface normal   */
+/*   into the dispersed phase (red, phi > 0: the droplets), proportional to   */
+/*   the dispersed density at y.  In the collision it acts on the mixture     */
+/*   like the constant body force (Guo source, half-force velocity shift).    */
+/* ------------------------------------------------------------------------ */
+
+/* Linear index of the point (x, y, z) + d c; 0 if it lies beyond a wall. */
+static int sample_point(const ref_params* p, int64_t x, int64_t y, int64_t z, const int c[3],
+                        int64_t d, int64_t* out) {
+  const int64_t n[3] = {p->nx, p->ny, p->nz};
+  int64_t t[3] = {x + d * c[0], y + d * c[1], z + d * c[2]};
+  for (int al = 0; al < 3; ++al) {
+    if (t[al] < 0 || t[al] >= n[al]) {
+      if (p->bb[al]) return 0;
+      t[al] = ((t[al] % n[al]) + n[al]) % n[al];
+    }
+  }
+  *out = t[0] + n[0] * (t[1] + n[1] * t[2]);
+  return 1;
+}
+
+static void nci_flags(const lattice_t* L, const ref_params* p, const double* phi,
+                      unsigned char* flag) {
+  const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+  const int64_t N = nx * ny * nz;
+  const double thr = -1.0 + p->nci_eps;
+  const int64_t d = p->nci_reach;
+  memset(flag, 0, (size_t)N);
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t n = x + nx * (y + ny * z);
+        if (!(phi[n] < thr)) continue;  /* not a bulk node */
+        for (int a = 0; a < L->q; ++a) {
+          const int b = L->opp[a];
+          if (b <= a) continue;  /* each pair of opposite directions once; skips rest */
+          int64_t ip, im;
+          if (!sample_point(p, x, y, z, L->c[a], d, &ip)) continue;
+          if (!sample_point(p, x, y, z, L->c[b], d, &im)) continue;
+          if (phi[ip] > thr && phi[im] > thr) {
+            flag[ip] = 1;
+            flag[im] = 1;
+          }
+        }
+      }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exported API                                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -435,9 +510,10 @@ static void step_one_species(const lattice_t* L, const ref_params* p, const doub
       }
 }
 
-/* One colour-gradient step, two species: f[2][Q][N] -> fnew. */
+/* One colour-gradient step, two species: f[2][Q][N] -> fnew.  flag[N] is
+ * scratch for the near-contact flags (NULL when they are off). */
 static void step_two_species(const lattice_t* L, const ref_params* p, const double* f,
-                             double* fnew, double* phi) {
+                             double* fnew, double* phi, unsigned char* flag) {
   const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
   const int64_t N = nx * ny * nz;
   const int Q = L->q;
@@ -445,6 +521,7 @@ static void step_two_species(const lattice_t* L, const ref_params* p, const doub
   double B[27];
   weights_B(L, B);
   phase_field(L, p, f, N, phi);
+  if (flag) nci_flags(L, p, phi, flag);
 #pragma omp parallel for collapse(2) schedule(static)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
@@ -457,12 +534,15 @@ static void step_two_species(const lattice_t* L, const ref_params* p, const doub
           rr += fr;
           rb += fb;
         }
-        collide(L, p, g, gpc);
         const double rho = rr + rb;
         double G[3];
         gradient(L, p, phi, x, y, z, G);
         const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
         const double Gn = sqrt(G2);
+        double Ft[3] = {p->force[0], p->force[1], p->force[2]};
+        if (flag && flag[n] && G2 > 1e-20)
+          for (int al = 0; al < 3; ++al) Ft[al] += p->nci_strength * rr * G[al] / Gn;
+        collide_f(L, p, g, Ft, gpc);
         for (int a = 0; a < Q; ++a) {
           double cG = cdot(L, a, G);
           double c2 = (double)(L->c[a][0] * L->c[a][0] + L->c[a][1] * L->c[a][1] +
@@ -495,9 +575,12 @@ int ref_run(const ref_params* p, double* f, int64_t nsteps) {
   const int64_t total = (int64_t)p->species * L.q * N;
   double* fb = (double*)malloc((size_t)total * sizeof(double));
   double* phi = (p->species == 2) ? (double*)malloc((size_t)N * sizeof(double)) : NULL;
-  if (!fb || (p->species == 2 && !phi)) {
+  const int nci = p->species == 2 && p->nci_strength != 0.0;
+  unsigned char* flag = nci ? (unsigned char*)malloc((size_t)N) : NULL;
+  if (!fb || (p->species == 2 && !phi) || (nci && !flag)) {
     free(fb);
     free(phi);
+    free(flag);
     return -2;
   }
   double* cur = f;
@@ -506,13 +589,45 @@ int ref_run(const ref_params* p, double* f, int64_t nsteps) {
     if (p->species == 1)
       step_one_species(&L, p, cur, nxt);
     else
-      step_two_species(&L, p, cur, nxt, phi);
+      step_two_species(&L, p, cur, nxt, phi, flag);
     double* t = cur;
     cur = nxt;
     nxt = t;
   }
   if (cur != f) memcpy(f, cur, (size_t)total * sizeof(double));
   free(fb);
+  free(phi);
+  free(flag);
+  return 0;
+}
+
+/* Near-contact flags and forces of the current two-species populations f:
+ * flag[N] (0/1) from the flagging pass, force[3 N] (x, then y, then z) the
+ * near-contact force of each node (without the constant body force). */
+int ref_nci(const ref_params* p, const double* f, unsigned char* flag, double* force) {
+  lattice_t L;
+  if (check_params(p, &L) != 0 || p->species != 2) return -1;
+  const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+  const int64_t N = nx * ny * nz;
+  const int Q = L.q;
+  double* phi = (double*)malloc((size_t)N * sizeof(double));
+  if (!phi) return -2;
+  phase_field(&L, p, f, N, phi);
+  nci_flags(&L, p, phi, flag);
+  for (int64_t z = 0; z < nz; ++z)
+    for (int64_t y = 0; y < ny; ++y)
+      for (int64_t x = 0; x < nx; ++x) {
+        const int64_t n = x + nx * (y + ny * z);
+        double G[3], rr = 0.0;
+        for (int a = 0; a < Q; ++a) rr += f[(int64_t)a * N + n];
+        gradient(&L, p, phi, x, y, z, G);
+        const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        for (int al = 0; al < 3; ++al) {
+          force[(int64_t)al * N + n] = 0.0;
+          if (flag[n] && G2 > 1e-20)
+            force[(int64_t)al * N + n] = p->nci_strength * rr * G[al] / sqrt(G2);
+        }
+      }
   free(phi);
   return 0;
 }

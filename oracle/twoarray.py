@@ -61,7 +61,11 @@ def _collide(g, c, w, D, tau, rho0, F, order):
     wq = w.reshape((-1,) + (1,) * (g.ndim - 1))
     rho = g.sum(axis=0)
     j = np.einsum("qa,q...->a...", cd, g)
-    Fv = np.asarray(F[:D], dtype=np.float64).reshape((D,) + (1,) * (g.ndim - 1))
+    Fv = np.asarray(F, dtype=np.float64)
+    if Fv.ndim == 1:  # one constant force, else a force field F[alpha, ...]
+        Fv = Fv[:D].reshape((D,) + (1,) * (g.ndim - 1))
+    else:
+        Fv = Fv[:D]
     u = (j + 0.5 * Fv) / rho0
     uu = np.einsum("a...,b...->ab...", u, u)
     cu = np.einsum("qa,a...->q...", cd, u)
@@ -139,6 +143,29 @@ def _gradient(phi, c, w, bb):
     return G / CS2
 
 
+def _nci_force(ph, rr, G, G2, c, bb, strength, eps, reach, D):
+    """Near-contact force field (Section 2.2) in gather form: node y is
+    flagged when it is not bulk and, for some direction c, the node
+    y - d c is bulk while y - 2 d c is not (that bulk node then sees
+    interfaces on both sides along c); points beyond a wall do not count.
+    Flagged nodes with a defined gradient get strength * rho_R * G/|G|."""
+    thr = -1.0 + eps
+    flag = np.zeros(ph.shape, dtype=bool)
+    for ca in c:
+        if not ca.any():
+            continue
+        k1 = reach * ca
+        mid = np.roll(ph, shift=(k1[2], k1[1], k1[0]), axis=(0, 1, 2))
+        far = np.roll(ph, shift=(2 * k1[2], 2 * k1[1], 2 * k1[0]), axis=(0, 1, 2))
+        ok = (_inside_after_shift(ph.shape, ca, bb, -reach)
+              & _inside_after_shift(ph.shape, ca, bb, -2 * reach))
+        flag |= ok & (mid < thr) & (far > thr)
+    flag &= ph > thr
+    big = G2 > 1e-20
+    scale = np.where(flag & big, strength * rr / np.sqrt(np.where(big, G2, 1.0)), 0.0)
+    return flag, scale[None] * G[:D]
+
+
 _B = {
     9: {0: -4 / 27, 1: 2 / 27, 2: 5 / 108},
     19: {0: -1 / 3, 1: 1 / 18, 2: 1 / 36},
@@ -195,7 +222,12 @@ def simulate(p, rho, u, nsteps, phi=None):
             G = _gradient(ph, c, w, p.bb)
             G2 = (G * G).sum(axis=0)
             Gn = np.sqrt(G2)
-            gpc = _collide(fr + fb, c, w, D, p.tau, p.rho0, F, p.order)
+            Fs = F
+            if p.nci_strength != 0.0:
+                _, Fn = _nci_force(ph, rr, G, G2, c, p.bb, p.nci_strength, p.nci_eps,
+                                   p.nci_reach, D)
+                Fs = np.asarray(F[:D], dtype=np.float64).reshape((D, 1, 1, 1)) + Fn
+            gpc = _collide(fr + fb, c, w, D, p.tau, p.rho0, Fs, p.order)
             cG = np.einsum("qa,a...->q...", c.astype(np.float64), G)
             big = (G2 > 1e-20)[None]
             safe = np.where(big, G2[None], 1.0)
