@@ -47,8 +47,8 @@ enum lb_status {
   LB_ENONFINITE = -5    /* non-finite value in input or in the evolved state */
 };
 
-/* Velocity sets (Section 2: "q depending on the dimensionality and isotropy
- * of the lattice"); textbook weights, cs^2 = 1/3. */
+/* Velocity sets (Section 2: the number of discrete velocities follows from
+ * the lattice's dimension and isotropy); textbook weights, cs^2 = 1/3. */
 enum lb_lattice { LB_D2Q9 = 9, LB_D3Q19 = 19, LB_D3Q27 = 27 };
 
 /* Boundary condition of one axis, applied at both ends of the axis.
@@ -85,8 +85,8 @@ typedef struct lb_params {
   double tau;             /* relaxation time, omega = 1/tau; tau > 1/2 */
   double rho0;            /* bulk density of the incompressible equilibrium
                              (eq. equil); > 0 */
-  double force[3];        /* constant body-force density (Section 2 "forcing
-                             terms"; scheme not given there): Guo's source
+  double force[3];        /* constant body-force density (Section 2 allows a
+                             body force but gives no scheme): Guo's source
                              term, so each node's momentum gains F per step
                              and u = (j + F/2)/rho0 */
   double sigma;           /* colour-gradient surface tension (species = 2) */

@@ -17,6 +17,16 @@ namespace lbk {
 
 constexpr int kRedBlocks = 1024;  // blocks of the conservation reduction
 
+// Grid of `blocks` 256-thread blocks: one dimension holds at most 2^32
+// work-items, so larger launches lay their blocks out x-fastest over
+// (x, y); kernels number them with flat_block() and drop the blocks past
+// the end.  Enough for any domain lb_validate accepts (y <= 65535).
+constexpr int64_t kMaxGridX = (int64_t(1) << 24) - 1;
+inline dim3 grid_of(int64_t blocks) {
+  if (blocks <= kMaxGridX) return dim3((unsigned)blocks);
+  return dim3((unsigned)kMaxGridX, (unsigned)((blocks + kMaxGridX - 1) / kMaxGridX));
+}
+
 struct Layout {
   int Q = 0, D = 0, M = 0, species = 1;
   size_t ssize = 0, csize = 0;  // bytes per stored population / per moment
@@ -113,8 +123,8 @@ struct ImplT {
   static hipError_t moments(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     const int64_t threads = p.npad / V1;
-    hipLaunchKernelGGL((k_moments<L, S, C, V1>), dim3((unsigned)((threads + 255) / 256)),
-                       dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
+    hipLaunchKernelGGL((k_moments<L, S, C, V1>), grid_of((threads + 255) / 256), dim3(256), 0,
+                       h->stream, (const S*)h->f, (C*)h->m, p);
     return hipGetLastError();
   }
   template <int V>
@@ -123,7 +133,7 @@ struct ImplT {
     constexpr int HH = V / E;
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    const dim3 grid((unsigned)((waves + 3) / 4));
+    const dim3 grid = grid_of((waves + 3) / 4);
     // the instruction-bound FD sweeps get a variant without the padded-row
     // selects for aligned rows; elsewhere the selects cost no measurable time
     if (FD && p.px == p.nx)
@@ -173,8 +183,8 @@ struct ImplT {
     return p.nseg * p.ny * p.nz;
   }
   static hipError_t batch_moments(const void* d, int n, int64_t total, hipStream_t s) {
-    hipLaunchKernelGGL((k_moments_batch<L, 1, S, C, V1>), dim3((unsigned)total), dim3(256), 0, s,
-                       (const JobDesc<C>*)d, n);
+    hipLaunchKernelGGL((k_moments_batch<L, 1, S, C, V1>), grid_of(total), dim3(256), 0, s,
+                       (const JobDesc<C>*)d, n, total);
     return hipGetLastError();
   }
   template <int V>
@@ -182,7 +192,7 @@ struct ImplT {
     constexpr int E = V < EMAX ? V : EMAX;
     constexpr int HH = V / E;
     hipLaunchKernelGGL((k_stream_collide_batch<L, ORDER, 1, S, C, E, HH, FD>),
-                       dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const JobDesc<C>*)d,
+                       grid_of((total + 3) / 4), dim3(256), 0, s, (const JobDesc<C>*)d,
                        n, total);
     return hipGetLastError();
   }
@@ -234,15 +244,15 @@ struct ImplT2 {
   static hipError_t moments(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     const int64_t threads = p.npad / V1;
-    hipLaunchKernelGGL((k_moments2<L, S, C, V1>), dim3((unsigned)((threads + 255) / 256)),
-                       dim3(256), 0, h->stream, (const S*)h->f, (C*)h->m, p);
+    hipLaunchKernelGGL((k_moments2<L, S, C, V1>), grid_of((threads + 255) / 256), dim3(256), 0,
+                       h->stream, (const S*)h->f, (C*)h->m, p);
     return hipGetLastError();
   }
   template <int E>
   static hipError_t sc(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
-    const dim3 grid((unsigned)((waves + 3) / 4));
+    const dim3 grid = grid_of((waves + 3) / 4);
     if (p.nseg == 1 && !p.bbx && p.px == p.nx)
       hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, true>), grid, dim3(256), 0, h->stream,
                          (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
@@ -287,14 +297,14 @@ struct ImplT2 {
     return p.nseg * p.ny * p.nz;
   }
   static hipError_t batch_moments(const void* d, int n, int64_t total, hipStream_t s) {
-    hipLaunchKernelGGL((k_moments_batch<L, 2, S, C, V1>), dim3((unsigned)total), dim3(256), 0, s,
-                       (const JobDesc<C>*)d, n);
+    hipLaunchKernelGGL((k_moments_batch<L, 2, S, C, V1>), grid_of(total), dim3(256), 0, s,
+                       (const JobDesc<C>*)d, n, total);
     return hipGetLastError();
   }
   template <int E>
   static hipError_t bsc(const void* d, int n, int64_t total, hipStream_t s) {
     hipLaunchKernelGGL((k_stream_collide_batch<L, 2, 2, S, C, E, 1>),
-                       dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, (const JobDesc<C>*)d,
+                       grid_of((total + 3) / 4), dim3(256), 0, s, (const JobDesc<C>*)d,
                        n, total);
     return hipGetLastError();
   }

@@ -59,6 +59,13 @@ struct StepParams {
   C wall[6][3];
 };
 
+// Flat block number of a launch whose blocks are laid out x-fastest over a
+// 2D grid (grid_of in handle.hpp): one grid dimension holds at most 2^32
+// work-items, fewer than a large domain's wavefronts need.
+__device__ __forceinline__ int64_t flat_block() {
+  return (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+}
+
 // -------------------------------------------------------------------------
 // Blocked array layout.  The padded node range [0, npad) is cut into blocks of
 // B = 2^lb consecutive nodes; a region of NA arrays stores, block after
@@ -359,7 +366,7 @@ __device__ __forceinline__ void moments_body(const S* __restrict__ f, C* __restr
 template <class L, typename S, typename C, int V>
 __global__ __launch_bounds__(256) void k_moments(const S* __restrict__ f, C* __restrict__ m,
                                                  StepParams<C> p) {
-  moments_body<L, S, C, V>(f, m, p, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V);
+  moments_body<L, S, C, V>(f, m, p, (flat_block() * blockDim.x + threadIdx.x) * V);
 }
 
 // -------------------------------------------------------------------------
@@ -672,7 +679,7 @@ template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = fa
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
   StreamCollide<L, ORDER, S, C, E, H, FD, PAD>::run_wave(
-      m, f, p, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+      m, f, p, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // -------------------------------------------------------------------------

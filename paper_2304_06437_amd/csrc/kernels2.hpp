@@ -118,7 +118,7 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
 template <class L, typename S, typename C, int V>
 __global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __restrict__ m,
                                                   StepParams<C> p) {
-  moments2_body<L, S, C, V>(f, m, p, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V);
+  moments2_body<L, S, C, V>(f, m, p, (flat_block() * blockDim.x + threadIdx.x) * V);
 }
 
 // Index of the phase field of node n: the last of the M + 1 moment arrays.
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m
                                                          S* __restrict__ f, StepParams<C> p,
                                                          ColourParams<C> cp) {
   StreamCollide2<L, S, C, E, WHOLE>::run_wave(
-      m, f, p, cp, (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+      m, f, p, cp, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
 // Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.

@@ -36,9 +36,11 @@ __device__ __forceinline__ int job_of(const JobDesc<C>* __restrict__ jobs, int n
 
 template <class L, int SPECIES, typename S, typename C, int V>
 __global__ __launch_bounds__(256) void k_moments_batch(const JobDesc<C>* __restrict__ jobs,
-                                                       int njobs) {
-  const JobDesc<C>& J = jobs[job_of(jobs, njobs, (int64_t)blockIdx.x)];
-  const int64_t i0 = (((int64_t)blockIdx.x - J.start) * blockDim.x + threadIdx.x) * V;
+                                                       int njobs, int64_t total) {
+  const int64_t u = flat_block();
+  if (u >= total) return;  // block-uniform
+  const JobDesc<C>& J = jobs[job_of(jobs, njobs, u)];
+  const int64_t i0 = ((u - J.start) * blockDim.x + threadIdx.x) * V;
   if constexpr (SPECIES == 1)
     moments_body<L, S, C, V>((const S*)J.f, (C*)J.m, J.p, i0);
   else
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void k_moments_batch(const JobDesc<C>* __restr
 template <class L, int ORDER, int SPECIES, typename S, typename C, int E, int H, bool FD = false>
 __global__ __launch_bounds__(256) void k_stream_collide_batch(const JobDesc<C>* __restrict__ jobs,
                                                               int njobs, int64_t total) {
-  const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t w = flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (w >= total) return;  // wave-uniform
   const JobDesc<C>& J = jobs[job_of(jobs, njobs, w)];
   if constexpr (SPECIES == 1)

@@ -43,7 +43,7 @@ using namespace lbk;
 typedef unsigned int lb_u4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_copy(const lb_u4* __restrict__ src,
                                               lb_u4* __restrict__ dst, int64_t n16) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = flat_block() * blockDim.x + threadIdx.x;
   if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
@@ -536,8 +536,7 @@ int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   const int64_t n16 = (int64_t)(bytes / 16);
   if (n16 == 0) return LB_OK;
   const int64_t blocks = (n16 + 255) / 256;
-  if (blocks > 0x7fffffff) return LB_EINVAL;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+  hipLaunchKernelGGL(k_copy, grid_of(blocks), dim3(256), 0, (hipStream_t)hip_stream,
                      (const lb_u4*)src, (lb_u4*)dst, n16);
   return launch_status(hipGetLastError());
 }

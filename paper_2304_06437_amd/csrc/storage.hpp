@@ -26,18 +26,28 @@ struct Codec<float, float> {
   __device__ static inline float store(float c) { return c; }
 };
 
+// The stored value is the round-to-nearest-even image of the FP32 value c.
+// The empty asm pins c as an FP32 register value: without it the compiler
+// may fold the conversion into the FMA that produced c (v_fma_mix*_f16, one
+// rounding straight to 16 bits), whose result differs from rounding the
+// FP32 value where that value sits next to a 16-bit tie.
+__device__ __forceinline__ float fp32_value(float c) {
+  asm("" : "+v"(c));
+  return c;
+}
+
 template <>
 struct Codec<_Float16, float> {
   __device__ static inline float load(_Float16 s) { return (float)s; }
   // v_cvt_f16_f32 under the default round-to-nearest-even mode
-  __device__ static inline _Float16 store(float c) { return (_Float16)c; }
+  __device__ static inline _Float16 store(float c) { return (_Float16)fp32_value(c); }
 };
 
 // fptrunc to bfloat: round to nearest, ties to even (v_cvt_pk_bf16_f32 on gfx950)
 template <>
 struct Codec<__bf16, float> {
   __device__ static inline float load(__bf16 s) { return (float)s; }
-  __device__ static inline __bf16 store(float c) { return (__bf16)c; }
+  __device__ static inline __bf16 store(float c) { return (__bf16)fp32_value(c); }
 };
 
 // Streaming hints: population and moment arrays are touched once per sweep,
