@@ -251,6 +251,32 @@ int lb_batch_destroy(lb_batch* b);
  * streams. */
 int lb_step_batch(lb_handle* const* handles, const int64_t* nsteps, int count);
 
+/* Limits of lb_step_batch_noalloc: handles per call, and the bytes of its
+ * per-device descriptor array. */
+#define LB_NOALLOC_MAX_HANDLES 1024
+#define LB_NOALLOC_SCRATCH_BYTES (1u << 20)
+
+/* For callers that cannot allocate (code recorded into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc): lb_step_batch with no
+ * allocation of any kind, device or host.  Same arguments, grouping and
+ * results as lb_step_batch (bitwise), with these differences:
+ *   - the descriptor tables live in a fixed array of
+ *     LB_NOALLOC_SCRATCH_BYTES in the library's device code, one per GPU,
+ *     held until the process ends; they are written there by small kernels
+ *     on the handles' stream, so the call returns without waiting (like
+ *     lb_step) and is ordered with earlier and later work on that stream;
+ *   - steps are launched directly, never through a graph;
+ *   - every handle must have been created on the current HIP device.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * tables: two calls whose work overlaps on one GPU (different streams, or
+ * different threads without ordering between them) race and may step with
+ * each other's tables.  Calls on one stream are safe.
+ * LB_ENOMEM for more than LB_NOALLOC_MAX_HANDLES handles (the tables of up
+ * to that many always fit the array); LB_EINVAL as lb_step_batch, or for a
+ * handle created on another device or enqueueing on another stream.
+ * Nothing is enqueued when an error is returned before the first launch. */
+int lb_step_batch_noalloc(lb_handle* const* handles, const int64_t* nsteps, int count);
+
 /* ---- instrumentation ------------------------------------------------- */
 
 /* Start per-kernel timing: the next lb_step calls record HIP events around

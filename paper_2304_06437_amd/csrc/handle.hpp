@@ -51,6 +51,7 @@ struct lb_handle {
   void* m = nullptr;
   double* partial = nullptr;
   hipStream_t stream = nullptr;
+  int device = 0;  // HIP device current at lb_create
   int64_t steps = 0;
   int v2 = 1;  // nodes per lane of the stream-collide sweep
   lbk::StepParams<float> p32;

@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -262,6 +263,13 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
     }
     h->stream = (hipStream_t)hip_stream;
     h->v2 = h->L.v2;
+    {
+      const hipError_t de = hipGetDevice(&h->device);
+      if (de != hipSuccess) {
+        delete h;
+        return status_of(de);
+      }
+    }
     if (dev_mem) {
       if (((uintptr_t)dev_mem % kAlign) != 0) {
         delete h;
@@ -757,6 +765,196 @@ int lb_batch_destroy(lb_batch* b) {
   if (b->copied) (void)hipEventDestroy(b->copied);
   delete b;
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched step without allocation (lb_step_batch_noalloc)
+//
+// The descriptor tables live in a fixed per-device array instead of buffers
+// allocated per call.  They are written there by small kernels that carry
+// the descriptor bytes as kernel arguments, so no host staging buffer has to
+// outlive the call and nothing waits: every write is ordered on the
+// handles' stream after the previous segment's sweeps.  Host-side
+// bookkeeping uses fixed-size arrays on the stack.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kPutWords = 384;  // 3 KiB of descriptor bytes per write kernel
+constexpr int kMaxDevices = 64;
+
+struct ScratchPut {
+  uint64_t w[kPutWords];
+  uint32_t dst_word;  // first destination word in the scratch array
+  uint32_t nwords;
+};
+
+__global__ __launch_bounds__(kPutWords) void k_scratch_put(uint64_t* __restrict__ base,
+                                                           ScratchPut put) {
+  const uint32_t t = threadIdx.x;
+  if (t < put.nwords) base[put.dst_word + t] = put.w[t];
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (the host-side name of the array is not a device address).
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Accumulates descriptor bytes bound for consecutive scratch words and
+// flushes them as one write kernel when full or when the next bytes go
+// elsewhere.
+struct Putter {
+  uint64_t* base;
+  hipStream_t stream;
+  ScratchPut put;
+  hipError_t err = hipSuccess;
+  Putter(void* b, hipStream_t s) : base((uint64_t*)b), stream(s) {
+    put.dst_word = 0;
+    put.nwords = 0;
+  }
+  void flush() {
+    if (put.nwords == 0 || err != hipSuccess) {
+      put.nwords = 0;
+      return;
+    }
+    hipLaunchKernelGGL(k_scratch_put, dim3(1), dim3(kPutWords), 0, stream, base, put);
+    err = hipGetLastError();
+    put.nwords = 0;
+  }
+  // bytes: a multiple of 8; byte_off: a multiple of 8
+  void append(const void* src, size_t bytes, size_t byte_off) {
+    const uint32_t word = (uint32_t)(byte_off / 8);
+    const uint32_t n = (uint32_t)(bytes / 8);
+    if (put.nwords && (put.dst_word + put.nwords != word || put.nwords + n > kPutWords)) flush();
+    if (put.nwords == 0) put.dst_word = word;
+    std::memcpy(&put.w[put.nwords], src, bytes);
+    put.nwords += n;
+  }
+};
+
+struct NoAllocGroup {
+  const Impl* impl;
+  int v2;
+  int njobs;
+  size_t off_k1, off_k2;
+  int64_t units_k1, units_k2;
+};
+
+}  // namespace
+
+extern "C" {
+
+int lb_step_batch_noalloc(lb_handle* const* hs, const int64_t* nsteps, int count) {
+  if (count < 0 || (count > 0 && (!hs || !nsteps))) return LB_EINVAL;
+  if (count == 0) return LB_OK;
+  if (count > LB_NOALLOC_MAX_HANDLES) return LB_ENOMEM;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i] || nsteps[i] < 0) return LB_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return LB_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return LB_EINVAL;
+  }
+  int cur = -1;
+  LB_TRY_HIP(hipGetDevice(&cur));
+  if (cur != hs[0]->device) return LB_EINVAL;
+  void* sbase = nullptr;
+  LB_TRY_HIP(scratch_address(cur, &sbase));
+  const hipStream_t stream = hs[0]->stream;
+
+  // jobs by step count (ties in input order): each distinct count ends a
+  // segment over a fixed set of active jobs
+  int order[LB_NOALLOC_MAX_HANDLES];
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::sort(order, order + count, [&](int a, int c) {
+    return nsteps[a] < nsteps[c] || (nsteps[a] == nsteps[c] && a < c);
+  });
+
+  NoAllocGroup groups[LB_NOALLOC_MAX_HANDLES];
+  unsigned char desc[512];
+  int64_t done = 0;
+  for (int k = 0; k < count; ++k) {
+    const int64_t target = nsteps[order[k]];
+    if (target <= done) continue;
+    // active jobs grouped by kernel configuration, groups in order of first job
+    int ng = 0;
+    for (int i = 0; i < count; ++i) {
+      if (nsteps[i] <= done) continue;
+      int g = 0;
+      while (g < ng && !(groups[g].impl == hs[i]->impl && groups[g].v2 == hs[i]->v2)) ++g;
+      if (g == ng) {
+        groups[ng] = NoAllocGroup{hs[i]->impl, hs[i]->v2, 0, 0, 0, 0, 0};
+        ++ng;
+      }
+      ++groups[g].njobs;
+    }
+    size_t bytes = 0;
+    for (int g = 0; g < ng; ++g) {
+      const size_t tb = align_up(groups[g].impl->desc_size * groups[g].njobs, 256);
+      groups[g].off_k1 = bytes;
+      bytes += tb;
+      groups[g].off_k2 = bytes;
+      bytes += tb;
+    }
+    // the first segment holds every job, later ones subsets: only the first
+    // can exceed the array, and then nothing has been enqueued yet
+    if (bytes > LB_NOALLOC_SCRATCH_BYTES) return LB_ENOMEM;
+    Putter put(sbase, stream);
+    for (int g = 0; g < ng; ++g) {
+      NoAllocGroup& G = groups[g];
+      const size_t ds = G.impl->desc_size;
+      if (ds > sizeof(desc) || ds % 8) return LB_EUNSUPPORTED;
+      int64_t u1 = 0, u2 = 0;
+      int q = 0;
+      for (int i = 0; i < count; ++i) {
+        if (nsteps[i] <= done || hs[i]->impl != G.impl || hs[i]->v2 != G.v2) continue;
+        G.impl->fill_desc(hs[i], desc, u1);
+        put.append(desc, ds, G.off_k1 + (size_t)q * ds);
+        u1 += G.impl->units_moments(hs[i]);
+        ++q;
+      }
+      q = 0;
+      for (int i = 0; i < count; ++i) {
+        if (nsteps[i] <= done || hs[i]->impl != G.impl || hs[i]->v2 != G.v2) continue;
+        G.impl->fill_desc(hs[i], desc, u2);
+        put.append(desc, ds, G.off_k2 + (size_t)q * ds);
+        u2 += G.impl->units_sc(hs[i]);
+        ++q;
+      }
+      G.units_k1 = u1;
+      G.units_k2 = u2;
+    }
+    put.flush();
+    LB_TRY_HIP(put.err);
+    const char* tables = (const char*)sbase;
+    for (int64_t s = 0; s < target - done; ++s) {
+      for (int g = 0; g < ng; ++g)
+        LB_TRY_HIP(groups[g].impl->batch_moments(tables + groups[g].off_k1, groups[g].njobs,
+                                                 groups[g].units_k1, stream));
+      for (int g = 0; g < ng; ++g)
+        LB_TRY_HIP(groups[g].impl->batch_sc(tables + groups[g].off_k2, groups[g].njobs,
+                                            groups[g].units_k2, groups[g].v2, stream));
+    }
+    done = target;
+  }
+  for (int i = 0; i < count; ++i) hs[i]->steps += nsteps[i];
+  return LB_OK;
 }
 
 }  // extern "C"

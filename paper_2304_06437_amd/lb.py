@@ -105,6 +105,8 @@ def load():
     lib.lb_batch_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
     lib.lb_step_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.c_int]
+    lib.lb_step_batch_noalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.lb_batch_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.lb_batch_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -280,6 +282,20 @@ def lb_step_batch(handles, nsteps):
     hs = (ctypes.c_void_p * n)(*[h.value for h in handles])
     ns = (ctypes.c_int64 * n)(*[int(k) for k in nsteps])
     _check(load().lb_step_batch(hs, ns, n), "lb_step_batch")
+
+
+LB_NOALLOC_MAX_HANDLES = 1024
+LB_NOALLOC_SCRATCH_BYTES = 1 << 20
+
+
+def lb_step_batch_noalloc(handles, nsteps):
+    """Batched step of handles on one stream without any allocation: the
+    descriptor tables go to the library's fixed per-device array; returns
+    without waiting."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*[h.value for h in handles])
+    ns = (ctypes.c_int64 * max(n, 1))(*[int(k) for k in nsteps])
+    _check(load().lb_step_batch_noalloc(hs, ns, n), "lb_step_batch_noalloc")
 
 
 def lb_batch_set_graphs(b, enable: bool):

@@ -206,3 +206,19 @@ def test_one_hip_runtime_whatever_the_import_order():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
+
+def test_noalloc_batch_limits_checked_before_any_device_call():
+    import ctypes
+    lib = lb.load()
+    n = lb.LB_NOALLOC_MAX_HANDLES + 1
+    hs = (ctypes.c_void_p * n)()
+    ns = (ctypes.c_int64 * n)()
+    assert lib.lb_step_batch_noalloc(hs, ns, n) == lb.LB_ENOMEM
+    assert lib.lb_step_batch_noalloc(hs, ns, -1) == lb.LB_EINVAL
+    assert lib.lb_step_batch_noalloc(None, None, 0) == lb.LB_OK
+    assert lib.lb_step_batch_noalloc(hs, ns, 1) == lb.LB_EINVAL  # NULL handle
+    hdr = open(lb.HEADER).read()
+    assert f"#define LB_NOALLOC_MAX_HANDLES {lb.LB_NOALLOC_MAX_HANDLES}" in hdr
+    assert "#define LB_NOALLOC_SCRATCH_BYTES (1u << 20)" in hdr
+    assert lb.LB_NOALLOC_SCRATCH_BYTES == 1 << 20
