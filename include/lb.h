@@ -71,10 +71,15 @@ enum lb_storage {
  * LB_STORE_F64; the 32-bit-compute modes keep their moments in FP32. */
 enum lb_compute { LB_COMPUTE_F64 = 0, LB_COMPUTE_F32 = 1 };
 
-/* Problem statement (Sections 2-3).  Fill with lb_params_default first;
- * struct_size must be sizeof(lb_params) so the layout can grow. */
+/* Problem statement (Sections 2-3).  Fill with lb_params_default first.
+ * struct_size is the size of the caller's struct, so the layout can grow:
+ * the library accepts sizeof(lb_params) and the sizes of its earlier
+ * versions, LB_PARAMS_SIZE_V1 (up to `compute`) and LB_PARAMS_SIZE_V2 (up to
+ * `wall_velocity`); fields beyond the caller's size take their defaults
+ * (zero wall velocity, near-contact interactions off).  Any other size is
+ * LB_EINVAL. */
 typedef struct lb_params {
-  size_t struct_size;     /* = sizeof(lb_params) */
+  size_t struct_size;     /* = sizeof(lb_params), or an earlier version's size */
   int32_t lattice;        /* enum lb_lattice */
   int32_t hermite_order;  /* 2, or 3 (D3Q27 only): order of the Hermite
                              expansion of equilibrium and non-equilibrium
@@ -107,16 +112,35 @@ typedef struct lb_params {
                              non-zero normal component or a velocity on a
                              periodic axis, LB_EUNSUPPORTED with two species.
                              Zero (the default) = resting walls. */
+  /* Near-contact interactions between interfaces (Section 2.2; species = 2
+   * only; the paper gives the mechanism but no constants, so these are
+   * readings).  A bulk node x of the continuous phase, phi(x) < -1 +
+   * nci_eps, samples phi at x + d c_a and x - d c_a (d = nci_reach) for
+   * every pair of opposite lattice directions; when neither point is bulk,
+   * both are flagged.  A flagged node with a defined phase gradient G
+   * gets the body force nci_strength * rho_R * G/|G| in its collision (on
+   * top of `force`), pushing each interface back into its own droplet.
+   * lb_moments reports u = (j + force/2)/rho0 with the constant force only. */
+  double nci_strength;    /* force constant A >= 0; 0 (default) = off */
+  double nci_eps;         /* bulk threshold, 0 < eps < 2 (default 0.1) */
+  int32_t nci_reach;      /* sampling distance d, 1..8 lattice spacings (default 1) */
+  int32_t nci_reserved_;  /* 0 */
 } lb_params;
+
+/* struct_size values of the earlier versions of lb_params. */
+#define LB_PARAMS_SIZE_V1 ((size_t)offsetof(lb_params, wall_velocity))
+#define LB_PARAMS_SIZE_V2 ((size_t)offsetof(lb_params, nci_strength))
 
 typedef struct lb_handle lb_handle;
 
 /* Fill *p with a valid default problem (D3Q19, 32^3, periodic, tau 0.6,
- * rho0 1, no force, one species, FP32 storage and compute).  p != NULL. */
+ * rho0 1, no force, one species, FP32 storage and compute, resting walls,
+ * near-contact interactions off).  p != NULL. */
 void lb_params_default(lb_params* p);
 
 /* Exact number of device bytes lb_create needs for these parameters:
  * populations (species * Q arrays) + moments (M arrays) of npad nodes each,
+ * + npad bytes of near-contact flags when nci_strength > 0,
  * npad = px * ny * nz rounded up to the layout's block size, where the row
  * pitch px is nx rounded up to a multiple of the stream-collide sweep's
  * vector chunk (1 to 8 nodes; see lb_layout), each region 256-byte aligned,
@@ -225,7 +249,8 @@ typedef struct lb_batch lb_batch;
  * domains share launches. */
 int lb_batch_create(void* hip_stream, lb_batch** out);
 
-/* Advance handles[i] by nsteps[i] >= 0 steps (distinct handles, count >= 0).
+/* Advance handles[i] by nsteps[i] >= 0 steps (distinct handles, count >= 0;
+ * LB_EUNSUPPORTED for a handle with near-contact interactions on).
  * Handles with the same kernel configuration (lattice, Hermite order,
  * species, storage, compute, row vector width) share one moments launch and
  * one stream-collide launch per step; a handle whose step count is reached
@@ -272,8 +297,9 @@ int lb_step_batch(lb_handle* const* handles, const int64_t* nsteps, int count);
  * different threads without ordering between them) race and may step with
  * each other's tables.  Calls on one stream are safe.
  * LB_ENOMEM for more than LB_NOALLOC_MAX_HANDLES handles (the tables of up
- * to that many always fit the array); LB_EINVAL as lb_step_batch, or for a
- * handle created on another device or enqueueing on another stream.
+ * to that many always fit the array); LB_EINVAL and LB_EUNSUPPORTED as
+ * lb_step_batch, or LB_EINVAL for a handle created on another device or
+ * enqueueing on another stream.
  * Nothing is enqueued when an error is returned before the first launch. */
 int lb_step_batch_noalloc(lb_handle* const* handles, const int64_t* nsteps, int count);
 

@@ -34,7 +34,7 @@ struct Layout {
   int64_t px = 0;               // row pitch: storage nodes per x-row (>= nx)
   int v2 = 1;                   // nodes per lane of the stream-collide sweep
   int lb = 10;                  // log2 of the block size of the array layout
-  size_t f_off = 0, m_off = 0, r_off = 0, total = 0;
+  size_t f_off = 0, m_off = 0, n_off = 0, r_off = 0, total = 0;  // n: near-contact flags
 };
 
 struct Impl;
@@ -58,6 +58,11 @@ struct lb_handle {
   lbk::StepParams<double> p64;
   lbk::ColourParams<float> cp32;
   lbk::ColourParams<double> cp64;
+  // near-contact interactions (two species): flags, one byte per storage node
+  bool nci = false;
+  unsigned char* flag = nullptr;
+  lbk::NciParams<float> nq32;
+  lbk::NciParams<double> nq64;
   // per-kernel timing
   std::vector<hipEvent_t> ev;
   int64_t tcap = 0, tcount = 0;
@@ -98,6 +103,12 @@ template <>
 inline const ColourParams<float>& colour_of<float>(const lb_handle* h) { return h->cp32; }
 template <>
 inline const ColourParams<double>& colour_of<double>(const lb_handle* h) { return h->cp64; }
+template <typename C>
+inline const NciParams<C>& nci_of(const lb_handle* h);
+template <>
+inline const NciParams<float>& nci_of<float>(const lb_handle* h) { return h->nq32; }
+template <>
+inline const NciParams<double>& nci_of<double>(const lb_handle* h) { return h->nq64; }
 
 template <typename C>
 inline void fill_job_desc(const lb_handle* h, void* dst, int64_t start) {
@@ -247,6 +258,12 @@ struct ImplT2 {
     const int64_t threads = p.npad / V1;
     hipLaunchKernelGGL((k_moments2<L, S, C, V1>), grid_of((threads + 255) / 256), dim3(256), 0,
                        h->stream, (const S*)h->f, (C*)h->m, p);
+    if (h->nci) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_nci_flags<L, C>), grid_of((p.npad + 255) / 256), dim3(256), 0,
+                         h->stream, (const C*)h->m, h->flag, p, nci_of<C>(h));
+    }
     return hipGetLastError();
   }
   template <int E>
@@ -254,12 +271,19 @@ struct ImplT2 {
     const auto& p = params_of<C>(h);
     const int64_t waves = p.nseg * p.ny * p.nz;
     const dim3 grid = grid_of((waves + 3) / 4);
-    if (p.nseg == 1 && !p.bbx && p.px == p.nx)
+    const NciParams<C>& q = nci_of<C>(h);
+    if (h->nci)
+      hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, false, true>), grid, dim3(256), 0,
+                         h->stream, (const C*)h->m, (S*)h->f, p, colour_of<C>(h),
+                         (const unsigned char*)h->flag, q);
+    else if (p.nseg == 1 && !p.bbx && p.px == p.nx)
       hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, true>), grid, dim3(256), 0, h->stream,
-                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
+                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h),
+                         (const unsigned char*)nullptr, q);
     else
       hipLaunchKernelGGL((k_stream_collide2<L, S, C, E, false>), grid, dim3(256), 0, h->stream,
-                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h));
+                         (const C*)h->m, (S*)h->f, p, colour_of<C>(h),
+                         (const unsigned char*)nullptr, q);
     return hipGetLastError();
   }
   static hipError_t stream_collide(const lb_handle* h) {

@@ -13,6 +13,11 @@
 // Storage: set 0 holds the mixture shifted, g_a - t_a rho0 (so its velocity
 // keeps full precision), set 1 the red populations f_R,a unshifted.  The
 // moments sweep writes drho, j, Pi^neq and phi (M + 1 arrays).
+//
+// Near-contact interactions (Section 2.2, optional): after the moments
+// sweep a flag pass marks the interface nodes on which a short-range
+// repulsion acts; the stream-collide sweep adds the body force
+// A rho_R n to the collision of every flagged node (see k_nci_flags).
 #pragma once
 
 #include "kernels.hpp"
@@ -140,11 +145,121 @@ __device__ __forceinline__ C phi_at(const C* __restrict__ m, const StepParams<C>
   return m[phi_index<L>(p, trow_base + xx)];
 }
 
-// Full per-node state of node (x, y, z) by scalar loads (segment halos).
+// -------------------------------------------------------------------------
+// Near-contact interactions (Section 2.2).
+//
+// Flag pass, gather form of the paper's rule.  The paper sits on a bulk node
+// x of the continuous phase (phi(x) < -1 + eps), samples phi at x + d c_a
+// and x - d c_a for each pair of opposite lattice directions, and flags both
+// points when neither is bulk.  Seen from a node y, that is: y is flagged
+// when it is not bulk and, for some direction c_a, the node y - d c_a is
+// bulk while y - 2 d c_a is not.  Points beyond a bounce-back wall are not
+// sampled; periodic axes wrap.  One thread per storage node, padding nodes
+// get 0.
+// Force: a flagged node with a defined phase gradient G carries
+// F = A rho_R G/|G| (along the interface normal, into the dispersed red
+// phase), added to the constant body force in its collision.
+// -------------------------------------------------------------------------
+template <typename C>
+struct NciParams {
+  C strength;      // A
+  C thr;           // -1 + eps: phi below it is continuous-phase bulk
+  int32_t reach;   // sampling distance d in lattice spacings
+  int32_t pad_;
+};
+
+// Storage node of (x, y, z) + k c_A, or -1 when it lies beyond a wall.
+template <class L, int A, typename C>
+__device__ __forceinline__ int64_t shifted_node(const StepParams<C>& p, int64_t x, int64_t y,
+                                                int64_t z, int64_t k) {
+  int64_t t[3] = {x + k * L::c[A][0], y + k * L::c[A][1], z + k * L::c[A][2]};
+  const int64_t n[3] = {p.nx, p.ny, p.nz};
+  const int32_t bb[3] = {p.bbx, p.bby, p.bbz};
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    if (t[al] < 0 || t[al] >= n[al]) {
+      if (bb[al]) return -1;
+      t[al] = ((t[al] % n[al]) + n[al]) % n[al];
+    }
+  }
+  return t[0] + p.px * (t[1] + p.ny * t[2]);
+}
+
+// Is there a direction c_A (A >= A0, not the rest link) with y - d c_A bulk
+// and y - 2 d c_A not bulk?
+template <class L, typename C, int A = 1>
+__device__ __forceinline__ bool nci_sees_pair(const C* __restrict__ m, const StepParams<C>& p,
+                                              const NciParams<C>& q, int64_t x, int64_t y,
+                                              int64_t z) {
+  if constexpr (A < L::Q) {
+    const int64_t s1 = shifted_node<L, A>(p, x, y, z, -(int64_t)q.reach);
+    const int64_t s2 = shifted_node<L, A>(p, x, y, z, -2 * (int64_t)q.reach);
+    if (s1 >= 0 && s2 >= 0 && m[phi_index<L>(p, s1)] < q.thr && m[phi_index<L>(p, s2)] > q.thr)
+      return true;
+    return nci_sees_pair<L, C, A + 1>(m, p, q, x, y, z);
+  } else {
+    return false;
+  }
+}
+
 template <class L, typename C>
+__global__ __launch_bounds__(256) void k_nci_flags(const C* __restrict__ m,
+                                                   unsigned char* __restrict__ flag,
+                                                   StepParams<C> p, NciParams<C> q) {
+  const int64_t n = flat_block() * blockDim.x + threadIdx.x;
+  if (n >= p.npad) return;
+  const int64_t x = n % p.px, row = n / p.px;
+  bool fl = false;
+  if (x < p.nx && row < p.ny * p.nz) {
+    const int64_t y = row % p.ny, z = row / p.ny;
+    if (m[phi_index<L>(p, n)] > q.thr) fl = nci_sees_pair<L, C>(m, p, q, x, y, z);
+  }
+  flag[n] = fl ? 1 : 0;
+}
+
+// Post-collision coefficients of a flagged node: its collision sees the body
+// force F + A rho_R G/|G| (G the phase gradient, |G| = Gn > 0, xr = rho_R/rho).
+// The stored Pi^neq was formed with the velocity u = (j + F/2)/rho0 of the
+// constant force; the extra half force shifts u, so Pi^neq = P - drho cs2 I
+// - rho0 u u gains rho0 (u u - u' u').
+template <class L, typename C>
+__device__ __forceinline__ void nci_coefficients(const C (&m0)[MomentLayout<L>::M],
+                                                 const C (&G)[3], C Gn, C xr,
+                                                 const StepParams<C>& p, const NciParams<C>& q,
+                                                 C (&k)[CoefLayout<L, 2>::K]) {
+  using ML = MomentLayout<L>;
+  constexpr int D = L::D;
+  const C rho = p.rho0 + m0[ML::RHO];
+  const C scale = q.strength * (xr * rho) / Gn;
+  StepParams<C> pf = p;
+  C mm[ML::M];
+#pragma unroll
+  for (int i = 0; i < ML::M; ++i) mm[i] = m0[i];
+  C ug[D], un[D];
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    pf.F[al] = p.F[al] + scale * G[al];
+    pf.halfF[al] = C(0.5) * pf.F[al];
+    ug[al] = (mm[ML::J + al] + p.halfF[al]) * p.inv_rho0;
+    un[al] = (mm[ML::J + al] + pf.halfF[al]) * p.inv_rho0;
+  }
+#pragma unroll
+  for (int al = 0; al < D; ++al) {
+    mm[ML::PID + al] += p.rho0 * (ug[al] * ug[al] - un[al] * un[al]);
+#pragma unroll
+    for (int be = al + 1; be < D; ++be)
+      mm[ML::PIO + offdiag(al, be)] += p.rho0 * (ug[al] * ug[be] - un[al] * un[be]);
+  }
+  post_collision<L, 2, C>(mm, pf, k);
+}
+
+// Full per-node state of node (x, y, z) by scalar loads (segment halos).
+template <class L, typename C, bool NCI = false>
 __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>& p,
                                     const ColourParams<C>& cp, int64_t x, int64_t y, int64_t z,
-                                    C (&st)[ColourLayout<L>::KT]) {
+                                    C (&st)[ColourLayout<L>::KT],
+                                    const unsigned char* __restrict__ flag = nullptr,
+                                    const NciParams<C>& q = NciParams<C>{}) {
   using ML = MomentLayout<L>;
   using XL = ColourLayout<L>;
   constexpr int D = L::D;
@@ -213,6 +328,14 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
     st[XL::S] = cp.pert * Gn;
 #pragma unroll
     for (int al = 0; al < D; ++al) st[XL::N + al] = G[al] / Gn;
+    if constexpr (NCI) {
+      if (flag[n]) {
+        C kf[XL::K];
+        nci_coefficients<L, C>(mm, G, Gn, xr, p, q, kf);
+#pragma unroll
+        for (int i = 0; i < XL::K; ++i) st[i] = kf[i];
+      }
+    }
   } else {
     st[XL::S] = C(0);
 #pragma unroll
@@ -261,7 +384,7 @@ __device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], 
 // row is one periodic, unpadded segment (nseg = 1, no x walls, px = nx), so
 // the states beyond the row's two ends are those of its other end, taken
 // from the lanes that hold them instead of recomputed.
-template <class L, typename S, typename C, int E, bool WHOLE = false>
+template <class L, typename S, typename C, int E, bool WHOLE = false, bool NCI = false>
 struct StreamCollide2 {
   using ML = MomentLayout<L>;
   using XL = ColourLayout<L>;
@@ -389,9 +512,12 @@ struct StreamCollide2 {
     }
   }
 
+  // flag, q: near-contact flags (one byte per storage node) and parameters,
+  // read only when NCI.
   __device__ static void run_wave(const C* __restrict__ m, S* __restrict__ f,
                                   const StepParams<C>& p, const ColourParams<C>& cp,
-                                  int64_t wave) {
+                                  int64_t wave, const unsigned char* __restrict__ flag = nullptr,
+                                  const NciParams<C>& q = NciParams<C>{}) {
     constexpr int D = L::D;
     const int lane = threadIdx.x & 63;
     const int64_t rows = p.ny * p.nz;
@@ -409,8 +535,8 @@ struct StreamCollide2 {
 
     C own[E][KT];
     C phio[E];
+    C mv[M][E];  // the lane's moments (the near-contact force revisits them)
     {
-      C mv[M][E];
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         if (act) load_plain<C, E, false>(m + slot<M + 1>(p, rowbase + xs) + q * astride(p), mv[q]);
@@ -527,6 +653,16 @@ struct StreamCollide2 {
         own[e][XL::S] = cp.pert * Gn;
 #pragma unroll
         for (int al = 0; al < D; ++al) own[e][XL::N + al] = G[e][al] / Gn;
+        if constexpr (NCI) {
+          if (act && flag[rowbase + xs + e]) {
+            C mm[M], kf[XL::K];
+#pragma unroll
+            for (int i = 0; i < M; ++i) mm[i] = mv[i][e];
+            nci_coefficients<L, C>(mm, G[e], Gn, own[e][XL::XR], p, q, kf);
+#pragma unroll
+            for (int i = 0; i < XL::K; ++i) own[e][i] = kf[i];
+          }
+        }
       } else {
         own[e][XL::S] = C(0);
 #pragma unroll
@@ -559,7 +695,7 @@ struct StreamCollide2 {
           if (p.bbx) ok = false;
           else xl = p.nx - 1;
         }
-        if (ok) colour_state_scalar<L, C>(m, p, cp, xl, y, z, left);
+        if (ok) colour_state_scalar<L, C, NCI>(m, p, cp, xl, y, z, left, flag, q);
       }
       if (act && xs + E >= xend) {
         int64_t xr = xend;
@@ -568,7 +704,7 @@ struct StreamCollide2 {
           if (p.bbx) ok = false;
           else xr = 0;
         }
-        if (ok) colour_state_scalar<L, C>(m, p, cp, xr, y, z, right);
+        if (ok) colour_state_scalar<L, C, NCI>(m, p, cp, xr, y, z, right, flag, q);
       }
     }
     if (!act) return;
@@ -576,12 +712,14 @@ struct StreamCollide2 {
   }
 };
 
-template <class L, typename S, typename C, int E, bool WHOLE = false>
+template <class L, typename S, typename C, int E, bool WHOLE = false, bool NCI = false>
 __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m,
                                                          S* __restrict__ f, StepParams<C> p,
-                                                         ColourParams<C> cp) {
-  StreamCollide2<L, S, C, E, WHOLE>::run_wave(
-      m, f, p, cp, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
+                                                         ColourParams<C> cp,
+                                                         const unsigned char* __restrict__ flag,
+                                                         NciParams<C> q) {
+  StreamCollide2<L, S, C, E, WHOLE, NCI>::run_wave(
+      m, f, p, cp, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6), flag, q);
 }
 
 // Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.

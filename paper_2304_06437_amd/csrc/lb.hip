@@ -72,9 +72,33 @@ int lattice_q(int lattice) {
   return lattice == LB_D2Q9 ? 9 : lattice == LB_D3Q19 ? 19 : lattice == LB_D3Q27 ? 27 : 0;
 }
 
-int validate(const lb_params* p) {
-  if (!p) return LB_EINVAL;
-  if (p->struct_size != sizeof(lb_params)) return LB_EINVAL;
+// The caller's parameters as a full current-version struct: the first
+// struct_size bytes (one of the known version sizes) copied over the
+// defaults of the later fields.  False for an unknown size.
+bool normalize(const lb_params* in, lb_params* out) {
+  if (!in) return false;
+  const size_t sz = in->struct_size;
+  if (sz != sizeof(lb_params) && sz != LB_PARAMS_SIZE_V2 && sz != LB_PARAMS_SIZE_V1) return false;
+  lb_params_default(out);
+  std::memcpy(out, in, sz);
+  if (sz < sizeof(lb_params)) {
+    lb_params d;
+    lb_params_default(&d);
+    std::memcpy((char*)out + sz, (const char*)&d + sz, sizeof(lb_params) - sz);
+  }
+  out->struct_size = sizeof(lb_params);
+  return true;
+}
+
+int validate_full(const lb_params* p);
+
+int validate(const lb_params* in) {
+  lb_params p;
+  if (!normalize(in, &p)) return LB_EINVAL;
+  return validate_full(&p);
+}
+
+int validate_full(const lb_params* p) {
   const int Q = lattice_q(p->lattice);
   if (!Q) return LB_EINVAL;
   if (p->hermite_order != 2 && p->hermite_order != 3) return LB_EINVAL;
@@ -125,6 +149,13 @@ int validate(const lb_params* p) {
         moving = true;
       }
   if (moving && p->species == 2) return LB_EUNSUPPORTED;
+  // near-contact interactions: two species, finite constants in range
+  if (!(std::isfinite(p->nci_strength) && p->nci_strength >= 0.0)) return LB_EINVAL;
+  if (p->nci_strength > 0.0) {
+    if (p->species != 2) return LB_EINVAL;
+    if (!(std::isfinite(p->nci_eps) && p->nci_eps > 0.0 && p->nci_eps < 2.0)) return LB_EINVAL;
+    if (p->nci_reach < 1 || p->nci_reach > 8) return LB_EINVAL;
+  }
   // keep every index comfortably inside int64
   const double N = (double)p->nx * (double)p->ny * (double)p->nz;
   if (N > 4.0e12) return LB_EINVAL;
@@ -174,7 +205,9 @@ Layout layout_of(const lb_params* p) {
   L.npad = (ns + B - 1) / B * B;
   L.f_off = 0;
   L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
-  L.r_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
+  L.n_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
+  const bool nci = p->species == 2 && p->nci_strength > 0.0;
+  L.r_off = L.n_off + (nci ? align_up((size_t)L.npad, kAlign) : 0);
   L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
   return L;
 }
@@ -237,20 +270,27 @@ void lb_params_default(lb_params* p) {
   p->beta = 0.0;
   p->storage = LB_STORE_F32;
   p->compute = LB_COMPUTE_F32;
+  p->nci_strength = 0.0;
+  p->nci_eps = 0.1;
+  p->nci_reach = 1;
 }
 
 int lb_validate(const lb_params* p) { return validate(p); }
 
-size_t lb_required_bytes(const lb_params* p) {
-  if (validate(p) != LB_OK) return 0;
-  return layout_of(p).total;
+size_t lb_required_bytes(const lb_params* in) {
+  lb_params p;
+  if (!normalize(in, &p) || validate_full(&p) != LB_OK) return 0;
+  return layout_of(&p).total;
 }
 
-int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_stream,
+int lb_create(const lb_params* in, void* dev_mem, size_t dev_bytes, void* hip_stream,
               lb_handle** out) {
   if (!out) return LB_EINVAL;
   *out = nullptr;
-  const int st = validate(p);
+  lb_params pn;
+  if (!normalize(in, &pn)) return LB_EINVAL;
+  const lb_params* p = &pn;
+  const int st = validate_full(p);
   if (st != LB_OK) return st;
   try {
     lb_handle* h = new lb_handle();
@@ -300,6 +340,10 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
     const double beta = p->beta / cden;
     h->cp32 = {(float)pert, (float)beta};
     h->cp64 = {pert, beta};
+    h->nci = p->species == 2 && p->nci_strength > 0.0;
+    h->flag = h->nci ? (unsigned char*)((char*)h->base + h->L.n_off) : nullptr;
+    h->nq32 = {(float)p->nci_strength, (float)(-1.0 + p->nci_eps), p->nci_reach, 0};
+    h->nq64 = {p->nci_strength, -1.0 + p->nci_eps, p->nci_reach, 0};
     hipError_t e = hipMemsetAsync(h->base, 0, h->L.total, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -630,6 +674,9 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
     for (int k = 0; k < i; ++k)
       if (hs[k] == hs[i]) return LB_EINVAL;
   }
+  // the batched sweeps have no near-contact flag pass
+  for (int i = 0; i < count; ++i)
+    if (hs[i]->nci) return LB_EUNSUPPORTED;
   if (count == 0) return LB_OK;
   try {
     // segments of constant active set: jobs sorted by their step counts
@@ -871,6 +918,8 @@ int lb_step_batch_noalloc(lb_handle* const* hs, const int64_t* nsteps, int count
     for (int k = 0; k < i; ++k)
       if (hs[k] == hs[i]) return LB_EINVAL;
   }
+  for (int i = 0; i < count; ++i)
+    if (hs[i]->nci) return LB_EUNSUPPORTED;
   int cur = -1;
   LB_TRY_HIP(hipGetDevice(&cur));
   if (cur != hs[0]->device) return LB_EINVAL;

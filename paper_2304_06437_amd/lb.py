@@ -46,7 +46,16 @@ class lb_params(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("compute", ctypes.c_int32),
         ("wall_velocity", ctypes.c_double * 18),   # [axis][low, high][component]
+        ("nci_strength", ctypes.c_double),
+        ("nci_eps", ctypes.c_double),
+        ("nci_reach", ctypes.c_int32),
+        ("nci_reserved_", ctypes.c_int32),
     ]
+
+
+# struct_size of the earlier versions of lb_params (include/lb.h)
+LB_PARAMS_SIZE_V1 = lb_params.wall_velocity.offset
+LB_PARAMS_SIZE_V2 = lb_params.nci_strength.offset
 
 
 class LbError(RuntimeError):

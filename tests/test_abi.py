@@ -222,3 +222,43 @@ def test_noalloc_batch_limits_checked_before_any_device_call():
     assert f"#define LB_NOALLOC_MAX_HANDLES {lb.LB_NOALLOC_MAX_HANDLES}" in hdr
     assert "#define LB_NOALLOC_SCRATCH_BYTES (1u << 20)" in hdr
     assert lb.LB_NOALLOC_SCRATCH_BYTES == 1 << 20
+
+
+def test_params_struct_versions():
+    """Callers built against the earlier, shorter lb_params (no moving walls;
+    no near-contact fields) are accepted; unknown sizes are not."""
+    import ctypes
+    assert lb.LB_PARAMS_SIZE_V1 < lb.LB_PARAMS_SIZE_V2 < ctypes.sizeof(lb.lb_params)
+    full = lb.lb_params_default(lattice=19, nx=24, ny=20, nz=16)
+    want = lb.lb_required_bytes(full)
+    for size in (lb.LB_PARAMS_SIZE_V1, lb.LB_PARAMS_SIZE_V2):
+        p = lb.lb_params_default(lattice=19, nx=24, ny=20, nz=16)
+        # the tail beyond the caller's size is garbage the library must not read
+        raw = (ctypes.c_ubyte * ctypes.sizeof(lb.lb_params)).from_buffer(p)
+        for i in range(size, ctypes.sizeof(lb.lb_params)):
+            raw[i] = 0xFF
+        p.struct_size = size
+        assert lb.lb_validate(p) == lb.LB_OK
+        assert lb.lb_required_bytes(p) == want
+    for bad in (0, 8, lb.LB_PARAMS_SIZE_V1 - 8, ctypes.sizeof(lb.lb_params) + 8):
+        p = lb.lb_params_default()
+        p.struct_size = bad
+        assert lb.lb_validate(p) == lb.LB_EINVAL
+        assert lb.lb_required_bytes(p) == 0
+
+
+def test_near_contact_parameters():
+    two = dict(species=2, sigma=0.03, beta=0.7)
+    assert lb.lb_validate(lb.lb_params_default(nci_strength=0.1, **two)) == lb.LB_OK
+    assert lb.lb_validate(lb.lb_params_default(nci_strength=0.1)) == lb.LB_EINVAL  # one species
+    for kw in (dict(nci_strength=-0.1), dict(nci_strength=float("nan")),
+               dict(nci_strength=0.1, nci_eps=0.0), dict(nci_strength=0.1, nci_eps=2.0),
+               dict(nci_strength=0.1, nci_reach=0), dict(nci_strength=0.1, nci_reach=9)):
+        assert lb.lb_validate(lb.lb_params_default(**kw, **two)) == lb.LB_EINVAL, kw
+    # off: eps and reach are not looked at
+    assert lb.lb_validate(lb.lb_params_default(nci_strength=0.0, nci_reach=0, **two)) == lb.LB_OK
+    # the flag array: one byte per padded node, 256-byte aligned
+    p_off = lb.lb_params_default(nx=40, ny=24, nz=20, **two)
+    p_on = lb.lb_params_default(nx=40, ny=24, nz=20, nci_strength=0.1, **two)
+    extra = lb.lb_required_bytes(p_on) - lb.lb_required_bytes(p_off)
+    assert extra >= 40 * 24 * 20 and extra % 256 == 0 and extra < 2 * 40 * 24 * 20 + 8192
