@@ -65,6 +65,11 @@
 #include <omp.h>
 #endif
 
+/* Domains below this many nodes run their node loops on one thread: the
+ * per-step fork/join of a parallel loop costs more than the work there.  Each
+ * node's arithmetic is independent of the thread count. */
+#define OMP_MIN_NODES 16384
+
 #define CS2 (1.0 / 3.0)
 #define CS4 (CS2 * CS2)
 #define CS6 (CS4 * CS2)
@@ -342,7 +347,7 @@ static void phase_field(const lattice_t* L, const ref_params* p, const double* f
                         double* phi) {
   const int Q = L->q;
   (void)p;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OMP_MIN_NODES)
   for (int64_t n = 0; n < N; ++n) {
     double rr = 0.0, rb = 0.0;
     for (int a = 0; a < Q; ++a) {
@@ -467,7 +472,7 @@ int ref_init(const ref_params* p, const double* rho, const double* u, const doub
   if (check_params(p, &L) != 0) return -1;
   const int64_t N = p->nx * p->ny * p->nz;
   const int Q = L.q, D = L.d;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OMP_MIN_NODES)
   for (int64_t n = 0; n < N; ++n) {
     double uu[3] = {0.0, 0.0, 0.0};
     for (int al = 0; al < D; ++al) uu[al] = u[(int64_t)al * N + n];
@@ -492,7 +497,7 @@ static void step_one_species(const lattice_t* L, const ref_params* p, const doub
   const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
   const int64_t N = nx * ny * nz;
   const int Q = L->q;
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (N >= OMP_MIN_NODES)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x) {
@@ -522,7 +527,7 @@ static void step_two_species(const lattice_t* L, const ref_params* p, const doub
   weights_B(L, B);
   phase_field(L, p, f, N, phi);
   if (flag) nci_flags(L, p, phi, flag);
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (N >= OMP_MIN_NODES)
   for (int64_t z = 0; z < nz; ++z)
     for (int64_t y = 0; y < ny; ++y)
       for (int64_t x = 0; x < nx; ++x) {
@@ -642,7 +647,7 @@ int ref_moments(const ref_params* p, const double* f, double* rho, double* u, do
   if (check_params(p, &L) != 0) return -1;
   const int64_t N = p->nx * p->ny * p->nz;
   const int Q = L.q, D = L.d;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OMP_MIN_NODES)
   for (int64_t n = 0; n < N; ++n) {
     double fl[27], rr = 0.0, rb = 0.0;
     for (int a = 0; a < Q; ++a) {
