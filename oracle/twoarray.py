@@ -42,10 +42,10 @@ def velocity_set(kind: int):
     return c, np.array(ws), opp
 
 
-def _hermite(c, D):
+def _hermite(c, D, dtype=np.float64):
     """H0, H1[Q,D], H2[Q,D,D], H3[Q,D,D,D] evaluated at the lattice velocities."""
-    cd = c[:, :D].astype(np.float64)
-    I = np.eye(D)
+    cd = c[:, :D].astype(dtype)
+    I = np.eye(D, dtype=dtype)
     H2 = np.einsum("qa,qb->qab", cd, cd) - CS2 * I
     H3 = (np.einsum("qa,qb,qc->qabc", cd, cd, cd)
           - CS2 * (np.einsum("qa,bc->qabc", cd, I)
@@ -57,11 +57,11 @@ def _hermite(c, D):
 def _collide(g, c, w, D, tau, rho0, F, order):
     """Regularized collision of every node: g[Q,...] -> g^pc[Q,...]."""
     omega = 1.0 / tau
-    cd, H2, H3 = _hermite(c, D)
-    wq = w.reshape((-1,) + (1,) * (g.ndim - 1))
+    cd, H2, H3 = _hermite(c, D, g.dtype)
+    wq = w.astype(g.dtype).reshape((-1,) + (1,) * (g.ndim - 1))
     rho = g.sum(axis=0)
     j = np.einsum("qa,q...->a...", cd, g)
-    Fv = np.asarray(F, dtype=np.float64)
+    Fv = np.asarray(F, dtype=g.dtype)
     if Fv.ndim == 1:  # one constant force, else a force field F[alpha, ...]
         Fv = Fv[:D].reshape((D,) + (1,) * (g.ndim - 1))
     else:
@@ -134,7 +134,8 @@ def _stream(fpc, c, opp, bb, w=None, wall_u=None, rho0=1.0):
 def _gradient(phi, c, w, bb):
     """Isotropic gradient (1/cs2) sum_b t_b c_b phi(x + c_b); beyond a wall the
     node's own value is used."""
-    G = np.zeros((3,) + phi.shape)
+    G = np.zeros((3,) + phi.shape, dtype=phi.dtype)
+    w = w.astype(phi.dtype)
     for b in range(len(c)):
         nb = np.roll(phi, shift=(-c[b][2], -c[b][1], -c[b][0]), axis=(0, 1, 2))
         nb = np.where(_inside_after_shift(phi.shape, c[b], bb, +1), nb, phi)
@@ -172,20 +173,23 @@ _B = {
 }
 
 
-def simulate(p, rho, u, nsteps, phi=None):
+def simulate(p, rho, u, nsteps, phi=None, dtype=np.float64):
     """Equilibrium start from (rho, u[, phi]), nsteps steps, then moments.
 
     ``p`` is an ``oracle.Params``.  Returns the same dict as
-    ``oracle.moments``.
+    ``oracle.moments`` (float64 arrays).  ``dtype`` np.float32 runs every
+    array and constant in float32 (a plain float32 transcription of the same
+    step, used to measure the step's float32 rounding floor).
     """
     c, w, opp = velocity_set(p.lattice)
+    w = w.astype(dtype)
     D = p.D
     shape = (p.nz, p.ny, p.nx)
     Q = len(w)
-    rho = np.asarray(rho, dtype=np.float64).reshape(shape)
-    u = np.asarray(u, dtype=np.float64).reshape((D,) + shape)
+    rho = np.asarray(rho, dtype=dtype).reshape(shape)
+    u = np.asarray(u, dtype=dtype).reshape((D,) + shape)
     F = tuple(p.force)
-    cd = c[:, :D].astype(np.float64)
+    cd = c[:, :D].astype(dtype)
     wq = w.reshape(Q, 1, 1, 1)
 
     def feq_of(r, uv):
@@ -194,7 +198,7 @@ def simulate(p, rho, u, nsteps, phi=None):
         e = cu / CS2 + 0.5 * (cu / CS2) ** 2 - 0.5 * usq / CS2
         out = wq * (r[None] + p.rho0 * e)
         if p.order >= 3:
-            _, _, H3 = _hermite(c, D)
+            _, _, H3 = _hermite(c, D, dtype)
             uuu = np.einsum("a...,b...,c...->abc...", uv, uv, uv)
             out = out + wq * p.rho0 * np.einsum("qabc,abc...->q...", H3, uuu) / (6 * CS2**3)
         return out
@@ -209,11 +213,12 @@ def simulate(p, rho, u, nsteps, phi=None):
         g = f
         ph = None
     else:
-        phi = np.asarray(phi, dtype=np.float64).reshape(shape)
+        phi = np.asarray(phi, dtype=dtype).reshape(shape)
         fr = 0.5 * (1 + phi)[None] * f0
         fb = 0.5 * (1 - phi)[None] * f0
-        Bv = np.array([_B[p.lattice][int((ci * ci).sum())] for ci in c]).reshape(Q, 1, 1, 1)
-        norm_c = np.sqrt((c * c).sum(axis=1)).astype(np.float64)
+        Bv = np.array([_B[p.lattice][int((ci * ci).sum())] for ci in c],
+                      dtype=dtype).reshape(Q, 1, 1, 1)
+        norm_c = np.sqrt((c * c).sum(axis=1)).astype(dtype)
         omega = 1.0 / p.tau
         for _ in range(nsteps):
             rr, rb = fr.sum(axis=0), fb.sum(axis=0)
@@ -226,9 +231,9 @@ def simulate(p, rho, u, nsteps, phi=None):
             if p.nci_strength != 0.0:
                 _, Fn = _nci_force(ph, rr, G, G2, c, p.bb, p.nci_strength, p.nci_eps,
                                    p.nci_reach, D)
-                Fs = np.asarray(F[:D], dtype=np.float64).reshape((D, 1, 1, 1)) + Fn
+                Fs = np.asarray(F[:D], dtype=dtype).reshape((D, 1, 1, 1)) + Fn
             gpc = _collide(fr + fb, c, w, D, p.tau, p.rho0, Fs, p.order)
-            cG = np.einsum("qa,a...->q...", c.astype(np.float64), G)
+            cG = np.einsum("qa,a...->q...", c.astype(dtype), G)
             big = (G2 > 1e-20)[None]
             safe = np.where(big, G2[None], 1.0)
             pert = np.where(big, 2.25 * p.sigma * omega * Gn[None] * (wq * cG * cG / safe - Bv), 0.0)
@@ -241,10 +246,11 @@ def simulate(p, rho, u, nsteps, phi=None):
         g = fr + fb
         rr, rb = fr.sum(axis=0), fb.sum(axis=0)
         ph = (rr - rb) / (rr + rb)
+        masses = (float(fr.sum(dtype=np.float64)), float(fb.sum(dtype=np.float64)))
 
     r = g.sum(axis=0)
     j = np.einsum("qa,q...->a...", cd, g)
-    Fv = np.asarray(F[:D]).reshape((D, 1, 1, 1))
+    Fv = np.asarray(F[:D], dtype=dtype).reshape((D, 1, 1, 1))
     uo = (j + 0.5 * Fv) / p.rho0
     fe = feq_of(r, uo)
     Pi = np.einsum("qa,qb,q...->ab...", cd, cd, g - fe)
@@ -253,7 +259,10 @@ def simulate(p, rho, u, nsteps, phi=None):
     else:
         pineq = np.stack([Pi[0, 0], Pi[1, 1], Pi[2, 2], Pi[0, 1], Pi[0, 2], Pi[1, 2]])
     N = p.N
-    out = {"rho": r.reshape(N), "u": uo.reshape(D, N), "pineq": pineq.reshape(-1, N)}
+    f64 = np.float64
+    out = {"rho": r.reshape(N).astype(f64), "u": uo.reshape(D, N).astype(f64),
+           "pineq": pineq.reshape(-1, N).astype(f64)}
     if ph is not None:
-        out["phi"] = ph.reshape(N)
+        out["phi"] = ph.reshape(N).astype(f64)
+        out["mass_red"], out["mass_blue"] = masses
     return out

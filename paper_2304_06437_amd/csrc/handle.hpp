@@ -34,7 +34,9 @@ struct Layout {
   int64_t px = 0;               // row pitch: storage nodes per x-row (>= nx)
   int v2 = 1;                   // nodes per lane of the stream-collide sweep
   int lb = 10;                  // log2 of the block size of the array layout
-  size_t f_off = 0, m_off = 0, n_off = 0, r_off = 0, total = 0;  // n: near-contact flags
+  // regions: populations, moments, near-contact flags, reference colours,
+  // reduction scratch
+  size_t f_off = 0, m_off = 0, n_off = 0, c_off = 0, r_off = 0, total = 0;
 };
 
 struct Impl;
@@ -257,7 +259,7 @@ struct ImplT2 {
     const auto& p = params_of<C>(h);
     const int64_t threads = p.npad / V1;
     hipLaunchKernelGGL((k_moments2<L, S, C, V1>), grid_of((threads + 255) / 256), dim3(256), 0,
-                       h->stream, (const S*)h->f, (C*)h->m, p);
+                       h->stream, (const S*)h->f, (C*)h->m, p, colour_of<C>(h));
     if (h->nci) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -301,19 +303,19 @@ struct ImplT2 {
   static hipError_t init(const lb_handle* h, const double* stage, int64_t n0, int64_t cnt) {
     const auto& p = params_of<C>(h);
     hipLaunchKernelGGL((k_init2<L, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
-                       h->stream, stage, n0, cnt, (S*)h->f, p);
+                       h->stream, stage, n0, cnt, (S*)h->f, p, colour_of<C>(h));
     return hipGetLastError();
   }
   static hipError_t readout(const lb_handle* h, double* out, int64_t n0, int64_t cnt) {
     const auto& p = params_of<C>(h);
     hipLaunchKernelGGL((k_readout2<L, S, C>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
-                       h->stream, (const S*)h->f, out, n0, cnt, p);
+                       h->stream, (const S*)h->f, out, n0, cnt, p, colour_of<C>(h));
     return hipGetLastError();
   }
   static hipError_t conserved(const lb_handle* h) {
     const auto& p = params_of<C>(h);
     hipLaunchKernelGGL((k_conserved2<L, S, C>), dim3(kRedBlocks), dim3(256), 0, h->stream,
-                       (const S*)h->f, h->partial, h->L.N, p);
+                       (const S*)h->f, h->partial, h->L.N, p, colour_of<C>(h));
     return hipGetLastError();
   }
   static int64_t units_moments(const lb_handle* h) { return params_of<C>(h).npad / V1 / 256; }

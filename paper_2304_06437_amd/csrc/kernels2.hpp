@@ -11,8 +11,17 @@
 // node's own phi).  No perturbation and cos(theta) = 0 where |G|^2 <= 1e-20.
 //
 // Storage: set 0 holds the mixture shifted, g_a - t_a rho0 (so its velocity
-// keeps full precision), set 1 the red populations f_R,a unshifted.  The
-// moments sweep writes drho, j, Pi^neq and phi (M + 1 arrays).
+// keeps full precision).  Set 1 holds the red populations relative to a
+// per-node reference colour ref(x) in {0, 1} (one byte per storage node):
+//   r_a(x) = f_R,a(x) - ref(x) g_a(x),
+// i.e. the red populations themselves at a blue-dominant node (ref 0) and
+// minus the blue ones at a red-dominant node (ref 1): in both pure phases
+// the stored values are small, so FP32 spends its digits on the colour
+// field's deviations, not on t_a rho.  The stream-collide sweep sets ref(x)
+// = [phi(x) > 0] from the phase it reads, for every node it owns, and
+// encodes every link it writes into x with that same value; the next
+// moments sweep decodes with it: rho_R = sum_a r_a + ref rho.  The moments
+// sweep writes drho, j, Pi^neq and phi (M + 1 arrays).
 //
 // Near-contact interactions (Section 2.2, optional): after the moments
 // sweep a flag pass marks the interface nodes on which a short-range
@@ -63,14 +72,15 @@ static_assert(colour_weights_consistent<D3Q19>(), "D3Q19 colour weights");
 
 template <typename C>
 struct ColourParams {
-  C pert;   // (9/4) sigma omega / den
-  C beta;   // beta / den
+  C pert;                // (9/4) sigma omega / den
+  C beta;                // beta / den
+  unsigned char* ref;    // reference colour per storage node (see above)
 };
 
 // Per-node state carried along x in the two-species sweep:
 // post-collision coefficients of the mixture, then S = (9/4) sigma omega |G|
-// / den, the unit normal n (D), rho_R/rho, rho_R rho0 / (rho den) and
-// beta rho_R rho_B / (rho den).
+// / den, the unit normal n (D), rho_R/rho, rho_R rho0 / den,
+// beta rho_R rho_B / (rho den), rho_B/rho and rho_B rho0 / den.
 template <class L>
 struct ColourLayout {
   static constexpr int K = CoefLayout<L, 2>::K;
@@ -79,14 +89,33 @@ struct ColourLayout {
   static constexpr int XR = K + 1 + L::D;
   static constexpr int R0 = K + 2 + L::D;
   static constexpr int RB = K + 3 + L::D;
-  static constexpr int KT = K + 4 + L::D;
+  static constexpr int XB = K + 4 + L::D;
+  static constexpr int B0 = K + 5 + L::D;
+  static constexpr int KT = K + 6 + L::D;
 };
 
-// Moments sweep: mixture moments from set 0, red density from set 1, and
-// phi = (2 rho_R - rho)/rho.
+// V reference-colour bytes of consecutive storage nodes (an aligned block).
+template <int V>
+__device__ __forceinline__ void load_ref(const unsigned char* __restrict__ ref, int64_t n,
+                                         unsigned char (&out)[V]) {
+  if constexpr (V == 1) out[0] = ref[n];
+  else raw_load<V, false>(ref + n, out);
+}
+
+template <int V>
+__device__ __forceinline__ void store_ref(unsigned char* __restrict__ ref, int64_t n,
+                                          const unsigned char (&in)[V]) {
+  if constexpr (V == 1) ref[n] = in[0];
+  else raw_store<V, false>(ref + n, in);
+}
+
+// Moments sweep: mixture moments from set 0, red density from set 1 and
+// the reference colour, rho_R = sum_a r_a + ref rho, and
+// phi = (2 rho_R - rho)/rho = (2 ref - 1) + 2 (sum_a r_a)/rho.
 template <class L, typename S, typename C, int V>
 __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __restrict__ m,
-                                              const StepParams<C>& p, int64_t i0) {
+                                              const StepParams<C>& p, const ColourParams<C>& cp,
+                                              int64_t i0) {
   using ML = MomentLayout<L>;
   if (i0 >= p.npad) return;
   // population region: 2Q arrays (set 0, then set 1); moment region: M + 1
@@ -104,6 +133,8 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
 #pragma unroll
     for (int e = 0; e < V; ++e) rr[e] += r[e];
   }
+  unsigned char ref[V];
+  load_ref<V>(cp.ref, i0, ref);
   C out[ML::M + 1][V];
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -114,7 +145,7 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
 #pragma unroll
     for (int q = 0; q < ML::M; ++q) out[q][e] = me[q];
     const C rho = p.rho0 + me[ML::RHO];
-    out[ML::M][e] = (C(2) * rr[e] - rho) / rho;
+    out[ML::M][e] = (ref[e] ? C(1) : C(-1)) + C(2) * rr[e] / rho;
   }
 #pragma unroll
   for (int q = 0; q <= ML::M; ++q) store_plain<C, V>(m + ms + q * B, out[q]);
@@ -122,8 +153,8 @@ __device__ __forceinline__ void moments2_body(const S* __restrict__ f, C* __rest
 
 template <class L, typename S, typename C, int V>
 __global__ __launch_bounds__(256) void k_moments2(const S* __restrict__ f, C* __restrict__ m,
-                                                  StepParams<C> p) {
-  moments2_body<L, S, C, V>(f, m, p, (flat_block() * blockDim.x + threadIdx.x) * V);
+                                                  StepParams<C> p, ColourParams<C> cp) {
+  moments2_body<L, S, C, V>(f, m, p, cp, (flat_block() * blockDim.x + threadIdx.x) * V);
 }
 
 // Index of the phase field of node n: the last of the M + 1 moment arrays.
@@ -344,16 +375,21 @@ __device__ void colour_state_scalar(const C* __restrict__ m, const StepParams<C>
   st[XL::XR] = xr;
   st[XL::R0] = scaled<1, ColourWeights<L>::den>(xr * p.rho0);
   st[XL::RB] = cp.beta * xr * xb * rho;
+  st[XL::XB] = xb;
+  st[XL::B0] = scaled<1, ColourWeights<L>::den>(xb * p.rho0);
 }
 
-// Value of link A from a source node's state: (shifted mixture, red).
+// Value of link A from a source node's state: the shifted mixture gs and
+// the stored red value fr for a destination of reference colour ref.
 //   g*_a  = [regularized mixture]_a + S' (tmul_a (c_a.n)^2 - bmul_a)
-//   f_R,a = (rho_R/rho) g*_a + tmul_a rho_R rho0/(rho den)
-//           + beta' tmul_a (c_a.n)/|c_a|
-// with S' = S/den and beta' = beta rho_R rho_B/(rho den); the unshifted red
-// population is (rho_R/rho)(g*_a + t_a rho0) + recolouring.
+//   rec   = beta' tmul_a (c_a.n)/|c_a|
+//   ref 0: fr = f_R,a = (rho_R/rho)(g*_a + t_a rho0) + rec
+//   ref 1: fr = f_R,a - (g*_a + t_a rho0) = -f_B,a = rec - (rho_B/rho)(g*_a + t_a rho0)
+// with S' = S/den and beta' = beta rho_R rho_B/(rho den); both forms are
+// evaluated from small terms (no cancellation of t_a rho0 sized values).
 template <class L, int A, typename C>
-__device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], C& gs, C& fr) {
+__device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], C& gs, C& fr,
+                                            bool ref) {
   using XL = ColourLayout<L>;
   using CW = ColourWeights<L>;
   constexpr int D = L::D;
@@ -375,8 +411,12 @@ __device__ __forceinline__ void colour_link(const C (&st)[ColourLayout<L>::KT], 
     rec = st[XL::RB] * (C(tm) * (cn * C(inv)));
   }
   gs = g;
-  fr = st[XL::XR] * g + C(tm) * st[XL::R0] + rec;
+  fr = ref ? rec - (st[XL::XB] * g + C(tm) * st[XL::B0])
+           : st[XL::XR] * g + C(tm) * st[XL::R0] + rec;
 }
+
+// Row index (0..8) of the target row offset (cy, cz) of a link.
+__host__ __device__ constexpr int row_id(int cy, int cz) { return (cy + 1) + 3 * (cz + 1); }
 
 // Stream-collide for two species.  One wavefront per x-row segment of 64 E
 // nodes (E per lane), as in StreamCollide; the phase-field gradient reads
@@ -394,13 +434,22 @@ struct StreamCollide2 {
 
   // tl: position of the row's last node x = nx - 1 in this lane's vector,
   // E if the vector does not hold it (nodes after it are padding).
+  // Reference colour (see the file header) of this lane's node e in the row
+  // at offset (cy, cz): bit row_id(cy, cz) E + e of the lane's mask.  A row
+  // beyond a wall holds the node's own value (its links come back into it).
+  __device__ __forceinline__ static bool ref_bit(uint64_t mask, int row, int e) {
+    return (mask >> (row * E + e)) & 1;
+  }
+
   template <int A>
   __device__ __forceinline__ static void link(S* __restrict__ f, const StepParams<C>& p,
                                               const C (&own)[E][KT], const C (&left)[KT],
                                               const C (&right)[KT], int64_t xs, int tl,
-                                              int64_t y, int64_t z, int64_t rowbase) {
+                                              int64_t y, int64_t z, int64_t rowbase,
+                                              uint64_t mask) {
     constexpr int cx = L::c[A][0], cy = L::c[A][1], cz = L::c[A][2];
     constexpr int AB = opposite<L>(A);
+    constexpr int trow = row_id(cy, cz), orow = row_id(0, 0);
     int64_t ty = y + cy, tz = z + cz;
     bool row_in = true;
     if (cy != 0 && (ty < 0 || ty >= p.ny)) {
@@ -417,28 +466,24 @@ struct StreamCollide2 {
       C gv[E], rv[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
+        const bool rf = ref_bit(mask, trow, e);
         if constexpr (cx == 0) {
-          colour_link<L, A, C>(own[e], gv[e], rv[e]);
+          colour_link<L, A, C>(own[e], gv[e], rv[e], rf);
         } else if constexpr (cx > 0) {
-          if (e > 0) colour_link<L, A, C>(own[e > 0 ? e - 1 : 0], gv[e], rv[e]);
-          else colour_link<L, A, C>(left, gv[e], rv[e]);
+          if (e > 0) colour_link<L, A, C>(own[e > 0 ? e - 1 : 0], gv[e], rv[e], rf);
+          else colour_link<L, A, C>(left, gv[e], rv[e], rf);
         } else {
-          if (e < E - 1) colour_link<L, A, C>(own[e < E - 1 ? e + 1 : 0], gv[e], rv[e]);
-          else colour_link<L, A, C>(right, gv[e], rv[e]);
+          if (e < E - 1) colour_link<L, A, C>(own[e < E - 1 ? e + 1 : 0], gv[e], rv[e], rf);
+          else colour_link<L, A, C>(right, gv[e], rv[e], rf);
         }
       }
       const bool padded = p.px != p.nx;  // wave-uniform
       if constexpr (cx < 0 && E > 1) {
         if (padded) {
           // the last node of a padded row takes source x + 1 from right
-          C gr, rr;
-          colour_link<L, A, C>(right, gr, rr);
 #pragma unroll
           for (int e = 0; e < E - 1; ++e)
-            if (e == tl) {
-              gv[e] = gr;
-              rv[e] = rr;
-            }
+            if (e == tl) colour_link<L, A, C>(right, gv[e], rv[e], ref_bit(mask, trow, e));
         }
       }
       // the E nodes from t on lie in one block
@@ -466,7 +511,8 @@ struct StreamCollide2 {
     } else {
       C gv[E], rv[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) colour_link<L, A, C>(own[e], gv[e], rv[e]);
+      for (int e = 0; e < E; ++e)
+        colour_link<L, A, C>(own[e], gv[e], rv[e], ref_bit(mask, orow, e));
       const int64_t t = slot<2 * L::Q>(p, rowbase + xs);
       if (p.px != p.nx) {
 #pragma unroll
@@ -484,7 +530,7 @@ struct StreamCollide2 {
           for (int e = 0; e < E; ++e)
             if (e == tl) {
               C g, r;
-              colour_link<L, A, C>(own[e], g, r);
+              colour_link<L, A, C>(own[e], g, r, ref_bit(mask, orow, e));
               const int64_t t = slot<2 * L::Q>(p, rowbase + xs + e);
               f[t + AB * astride(p)] = Codec<S, C>::store(g);
               f[t + (L::Q + AB) * astride(p)] = Codec<S, C>::store(r);
@@ -492,7 +538,7 @@ struct StreamCollide2 {
         }
         if (cx < 0 && xs == 0) {
           C g, r;
-          colour_link<L, A, C>(own[0], g, r);
+          colour_link<L, A, C>(own[0], g, r, ref_bit(mask, orow, 0));
           const int64_t t = slot<2 * L::Q>(p, rowbase);
           f[t + AB * astride(p)] = Codec<S, C>::store(g);
           f[t + (L::Q + AB) * astride(p)] = Codec<S, C>::store(r);
@@ -505,10 +551,11 @@ struct StreamCollide2 {
   __device__ __forceinline__ static void links(S* __restrict__ f, const StepParams<C>& p,
                                                const C (&own)[E][KT], const C (&left)[KT],
                                                const C (&right)[KT], int64_t xs, int tl,
-                                               int64_t y, int64_t z, int64_t rowbase) {
+                                               int64_t y, int64_t z, int64_t rowbase,
+                                               uint64_t mask) {
     if constexpr (A < L::Q) {
-      link<A>(f, p, own, left, right, xs, tl, y, z, rowbase);
-      links<A + 1>(f, p, own, left, right, xs, tl, y, z, rowbase);
+      link<A>(f, p, own, left, right, xs, tl, y, z, rowbase, mask);
+      links<A + 1>(f, p, own, left, right, xs, tl, y, z, rowbase, mask);
     }
   }
 
@@ -563,10 +610,13 @@ struct StreamCollide2 {
         own[e][XL::XR] = xr;
         own[e][XL::R0] = scaled<1, ColourWeights<L>::den>(xr * p.rho0);
         own[e][XL::RB] = cp.beta * xr * xb * rho;
+        own[e][XL::XB] = xb;
+        own[e][XL::B0] = scaled<1, ColourWeights<L>::den>(xb * p.rho0);
       }
     }
     // phase-field gradient of this lane's nodes from the rows around it
     C G[E][3];
+    uint64_t mask = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) G[e][0] = G[e][1] = G[e][2] = C(0);
 #pragma unroll
@@ -604,6 +654,10 @@ struct StreamCollide2 {
 #pragma unroll
           for (int e = 0; e < E; ++e) pv[e] = phio[e];
         }
+        // reference colours of the nodes this lane writes into in this row
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (pv[e] > C(0)) mask |= uint64_t(1) << (row_id(dy, dz) * E + e);
         // x-neighbours of the lane's first and last node in this row
         C pl = lane_from_below(pv[E - 1]);
         C pr = lane_from_above(pv[0]);
@@ -708,7 +762,14 @@ struct StreamCollide2 {
       }
     }
     if (!act) return;
-    links<0>(f, p, own, left, right, xs, tl, y, z, rowbase);
+    {
+      // this lane's nodes keep the reference colour every link into them uses
+      unsigned char rb[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) rb[e] = (e <= tl && phio[e] > C(0)) ? 1 : 0;
+      store_ref<E>(cp.ref, rowbase + xs, rb);
+    }
+    links<0>(f, p, own, left, right, xs, tl, y, z, rowbase, mask);
   }
 };
 
@@ -722,22 +783,26 @@ __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m
       m, f, p, cp, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6), flag, q);
 }
 
-// Initialisation: set 0 = f^eq - t rho0, set 1 = (1 + phi)/2 f^eq.
-// stage: (2 + D) x cnt doubles: drho, u, phi.
+// Initialisation: set 0 = f^eq - t rho0; red f_R = (1 + phi)/2 f^eq stored
+// relative to the reference colour [phi > 0]: (1 + phi)/2 f^eq, or
+// -(1 - phi)/2 f^eq.  stage: (2 + D) x cnt doubles: drho, u, phi.
 template <class L, typename S, typename C, int A>
 __device__ __forceinline__ void init2_links(S* __restrict__ f, int64_t B, int64_t fs,
-                                            const C (&k)[CoefLayout<L, 2>::K], C rho0, C xr) {
+                                            const C (&k)[CoefLayout<L, 2>::K], C rho0, C xr,
+                                            C xb, bool ref) {
   if constexpr (A < L::Q) {
     const C s = link_value<L, 2, A, C>(k);
     f[fs + A * B] = Codec<S, C>::store(s);
-    f[fs + (L::Q + A) * B] = Codec<S, C>::store(xr * (s + C(L::w[A]) * rho0));
-    init2_links<L, S, C, A + 1>(f, B, fs, k, rho0, xr);
+    const C feq = s + C(L::w[A]) * rho0;
+    f[fs + (L::Q + A) * B] = Codec<S, C>::store(ref ? -(xb * feq) : xr * feq);
+    init2_links<L, S, C, A + 1>(f, B, fs, k, rho0, xr, xb, ref);
   }
 }
 
 template <class L, typename S, typename C>
 __global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage, int64_t n0,
-                                               int64_t cnt, S* __restrict__ f, StepParams<C> p) {
+                                               int64_t cnt, S* __restrict__ f, StepParams<C> p,
+                                               ColourParams<C> cp) {
   using ML = MomentLayout<L>;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
@@ -747,7 +812,10 @@ __global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage,
   mm[ML::RHO] = (C)stage[i];
 #pragma unroll
   for (int al = 0; al < L::D; ++al) mm[ML::J + al] = p.rho0 * (C)stage[(int64_t)(1 + al) * cnt + i];
-  const C xr = (C(1) + (C)stage[(int64_t)(1 + L::D) * cnt + i]) * C(0.5);
+  const C phi = (C)stage[(int64_t)(1 + L::D) * cnt + i];
+  const C xr = (C(1) + phi) * C(0.5);
+  const C xb = (C(1) - phi) * C(0.5);
+  const bool ref = phi > C(0);
   StepParams<C> q = p;
 #pragma unroll
   for (int al = 0; al < 3; ++al) {
@@ -756,20 +824,24 @@ __global__ __launch_bounds__(256) void k_init2(const double* __restrict__ stage,
   }
   C k[CoefLayout<L, 2>::K];
   post_collision<L, 2, C>(mm, q, k);
-  init2_links<L, S, C, 0>(f, astride(p), slot<2 * L::Q>(p, node_at(p, n0 + i)), k, p.rho0, xr);
+  const int64_t n = node_at(p, n0 + i);
+  init2_links<L, S, C, 0>(f, astride(p), slot<2 * L::Q>(p, n), k, p.rho0, xr, xb, ref);
+  cp.ref[n] = ref ? 1 : 0;
 }
 
 // Read-out: rho, u, Pi^neq of the mixture and phi; (2 + D + D(D+1)/2) x cnt.
 template <class L, typename S, typename C>
 __global__ __launch_bounds__(256) void k_readout2(const S* __restrict__ f, double* __restrict__ out,
-                                                  int64_t n0, int64_t cnt, StepParams<C> p) {
+                                                  int64_t n0, int64_t cnt, StepParams<C> p,
+                                                  ColourParams<C> cp) {
   using ML = MomentLayout<L>;
   constexpr int D = L::D;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   C s[L::Q], me[ML::M];
   C rr = C(0);
-  const int64_t fs = slot<2 * L::Q>(p, node_at(p, n0 + i));
+  const int64_t n = node_at(p, n0 + i);
+  const int64_t fs = slot<2 * L::Q>(p, n);
 #pragma unroll
   for (int a = 0; a < L::Q; ++a) {
     s[a] = Codec<S, C>::load(f[fs + a * astride(p)]);
@@ -784,30 +856,36 @@ __global__ __launch_bounds__(256) void k_readout2(const S* __restrict__ f, doubl
 #pragma unroll
   for (int q = 0; q < D * (D + 1) / 2; ++q)
     out[(int64_t)(1 + D + q) * cnt + i] = (double)me[ML::PID + q];
-  out[(int64_t)(1 + D + D * (D + 1) / 2) * cnt + i] = (double)((C(2) * rr - rho) / rho);
+  out[(int64_t)(1 + D + D * (D + 1) / 2) * cnt + i] =
+      (double)((cp.ref[n] ? C(1) : C(-1)) + C(2) * rr / rho);
 }
 
 // FP64 reductions: drho, j (3), red mass.
 template <class L, typename S, typename C>
 __global__ __launch_bounds__(256) void k_conserved2(const S* __restrict__ f,
                                                     double* __restrict__ partial, int64_t N,
-                                                    StepParams<C> p) {
+                                                    StepParams<C> p, ColourParams<C> cp) {
   __shared__ double red[5][256];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
-    const int64_t fs = slot<2 * L::Q>(p, node_at(p, n));
+    const int64_t sn = node_at(p, n);
+    const int64_t fs = slot<2 * L::Q>(p, sn);
+    double drho = 0.0, red = 0.0;
 #pragma unroll
     for (int a = 0; a < L::Q; ++a) {
       const double s = (double)Codec<S, C>::load(f[fs + a * astride(p)]);
-      acc[0] += s;
+      drho += s;
 #pragma unroll
       for (int al = 0; al < 3; ++al) {
         if (L::c[a][al] > 0) acc[1 + al] += s;
         if (L::c[a][al] < 0) acc[1 + al] -= s;
       }
-      acc[4] += (double)Codec<S, C>::load(f[fs + (L::Q + a) * astride(p)]);
+      red += (double)Codec<S, C>::load(f[fs + (L::Q + a) * astride(p)]);
     }
+    acc[0] += drho;
+    // red mass of the node: sum_a r_a + ref rho
+    acc[4] += red + (cp.ref[sn] ? (double)p.rho0 + drho : 0.0);
   }
 #pragma unroll
   for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = acc[q];

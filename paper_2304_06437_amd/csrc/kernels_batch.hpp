@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_moments_batch(const JobDesc<C>* __restr
   if constexpr (SPECIES == 1)
     moments_body<L, S, C, V>((const S*)J.f, (C*)J.m, J.p, i0);
   else
-    moments2_body<L, S, C, V>((const S*)J.f, (C*)J.m, J.p, i0);
+    moments2_body<L, S, C, V>((const S*)J.f, (C*)J.m, J.p, J.cp, i0);
 }
 
 template <class L, int ORDER, int SPECIES, typename S, typename C, int E, int H, bool FD = false>

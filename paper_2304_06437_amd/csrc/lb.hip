@@ -2,10 +2,13 @@
 //
 // Device memory of one simulation (lb_required_bytes):
 //   f  species*Q population arrays, storage type: f_a - t_a rho0 (one
-//      species), or the mixture g_a - t_a rho0 and the red f_R,a (two)
+//      species), or the mixture g_a - t_a rho0 and the red set stored
+//      relative to each node's reference colour (two; see kernels2.hpp)
 //   m  M moment arrays (drho, j, Pi^neq, and phi for two species), compute type
+//   n  near-contact flags, one byte per storage node (two species, NCI on)
+//   c  reference colours, one byte per storage node (two species)
 //   r  FP64 partial sums of the conservation reduction
-// Both regions are blocked structures of arrays: the node range, padded to
+// f and m are blocked structures of arrays: the node range, padded to
 // npad (a multiple of the block size B, a power of two >= 1024), is cut into
 // blocks of B nodes, and block k of a region of NA arrays holds B elements of
 // each array in turn: element (a, n) at (n / B) NA B + a B + n % B.  B is 32
@@ -207,7 +210,8 @@ Layout layout_of(const lb_params* p) {
   L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
   L.n_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
   const bool nci = p->species == 2 && p->nci_strength > 0.0;
-  L.r_off = L.n_off + (nci ? align_up((size_t)L.npad, kAlign) : 0);
+  L.c_off = L.n_off + (nci ? align_up((size_t)L.npad, kAlign) : 0);
+  L.r_off = L.c_off + (p->species == 2 ? align_up((size_t)L.npad, kAlign) : 0);
   L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
   return L;
 }
@@ -338,8 +342,9 @@ int lb_create(const lb_params* in, void* dev_mem, size_t dev_bytes, void* hip_st
     const double cden = p->lattice == LB_D2Q9 ? 108.0 : 36.0;
     const double pert = 2.25 * p->sigma / p->tau / cden;
     const double beta = p->beta / cden;
-    h->cp32 = {(float)pert, (float)beta};
-    h->cp64 = {pert, beta};
+    unsigned char* ref = p->species == 2 ? (unsigned char*)((char*)h->base + h->L.c_off) : nullptr;
+    h->cp32 = {(float)pert, (float)beta, ref};
+    h->cp64 = {pert, beta, ref};
     h->nci = p->species == 2 && p->nci_strength > 0.0;
     h->flag = h->nci ? (unsigned char*)((char*)h->base + h->L.n_off) : nullptr;
     h->nq32 = {(float)p->nci_strength, (float)(-1.0 + p->nci_eps), p->nci_reach, 0};

@@ -68,8 +68,11 @@ def test_population_layout_matches_documentation(case):
     if species == 1:
         sets = [(got, fe - w[:, None] * 1.0)]
     else:
-        # set 0: mixture shifted; set 1: red populations
-        sets = [(got[:Q], fe[:Q] + fe[Q:] - w[:, None] * 1.0), (got[Q:], fe[:Q])]
+        # set 0: mixture shifted; set 1: red populations relative to the
+        # node's reference colour [phi > 0]: f_R, or f_R - g = -f_B
+        ref = (phi > 0)[None, :]
+        sets = [(got[:Q], fe[:Q] + fe[Q:] - w[:, None] * 1.0),
+                (got[Q:], np.where(ref, -fe[Q:], fe[:Q]))]
     tol = {"f32": 2e-7, "f16s": 1e-4, "f64": 1e-14}[storage]
     for g, ref in sets:
         err = np.abs(np.sort(g, axis=0) - np.sort(ref, axis=0)).max()

@@ -38,15 +38,19 @@ def _setup(case, storage="f32"):
 
 
 def _views(sim):
+    """The population region and the moment region (M arrays of npad nodes:
+    drho, j, Pi^neq, and phi for two species) of the device buffer."""
     import torch
 
-    pop_off, mom_off, _, _, _ = lb.lb_layout(sim.handle)
+    pop_off, mom_off, _, npad, _ = lb.lb_layout(sim.handle)
     buf = sim.buffer
     esz = 4 if sim.params.storage == lb.LB_STORE_F32 else 8
+    D = sim.D
+    M = 1 + D + D * (D + 1) // 2 + (1 if sim.params.species == 2 else 0)
     pops = buf[pop_off:mom_off]
-    moms = buf[mom_off:]
+    moms = buf[mom_off:mom_off + M * npad * esz]
     dt = torch.float32 if esz == 4 else torch.float64
-    return pops.view(dt), moms[: (len(moms) // esz) * esz].view(dt)
+    return pops.view(dt), moms.view(dt)
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))

@@ -1,55 +1,41 @@
 """GPU parity of the two-species colour-gradient step against the oracle.
 
-FP64 storage and arithmetic must reproduce the oracle to rounding.  FP32
-bars come from the rounding sensitivity of the colour-gradient step itself:
-a plain float32 transcription of the same two-array step (numpy, every
-array float32) differs from the FP64 oracle by 1.4e-5 (2D) and 4.8e-5 (3D)
-in max-relative velocity on the droplets-in-a-Taylor-Green-flow cases after
-1000 steps, and by 6.6e-6 to 8.2e-4 on the sharp-start cases (phi = +-1
-steps, random velocities).  The single-species bar (1e-5) is below that
-floor, so droplets in a flow are held to 5e-5 and sharp starts to 1e-4,
-with the errors printed.
+FP64 storage and arithmetic must reproduce the oracle to rounding.  FP32 is
+held to the float32 rounding floor of the step itself: the oracle's numpy
+twin run with every array in float32 (a plain float32 transcription of the
+same two-array step) differs from the FP64 oracle by the amounts recorded
+in tests/golden/two_species_fp32_floor.json (written by
+make_two_species_fp32_floor.py there, from oracle/ only): 9e-6 to 8e-4
+max-relative velocity on the sharp-start cases, 1.4e-5 (2D) and 4.8e-5 (3D)
+on droplets in a Taylor-Green flow after 1000 steps, i.e. above the
+single-species 1e-5 bar.  The GPU evaluates the same step in a different
+order (prescaled coefficients, fused multiply-adds, the minority-colour red
+set), so its rounding error is of the floor's size, not equal to it: each
+FP32 case must stay within max(1e-5, twice its floor), in velocity and in
+phi; the errors and their ratio to the floor are printed.  Species
+masses: the plain float32 transcription drifts by the recorded per-node
+amounts over 300 steps; the GPU path must not drift more.
 """
 import functools
+import json
+import os
 
 import numpy as np
 import pytest
 
 import oracle
-from paper_2304_06437_amd import inputs, lb
+from paper_2304_06437_amd import lb
 from paper_2304_06437_amd.sim import Simulation, make_params, max_rel, run
+from two_species_cases import CASES, CONSERVATION, FLOW_CASES, flow_state, sharp_state
 
 pytestmark = pytest.mark.gpu
 
+_FLOOR = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                     "two_species_fp32_floor.json")))
+
 
 def _state(lattice, shape, seed):
-    nx, ny, nz = shape
-    N = nx * ny * nz
-    D = 2 if lattice == 9 else 3
-    rng = np.random.default_rng(seed)
-    x = np.arange(N) % nx
-    y = (np.arange(N) // nx) % ny
-    z = np.arange(N) // (nx * ny)
-    phi = -np.ones(N)
-    for _ in range(3):
-        c = rng.uniform(0, 1, 3) * np.array(shape)
-        R = 0.22 * min(s for s in shape if s > 1)
-        d2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + ((z - c[2]) ** 2 if D == 3 else 0)
-        phi[d2 <= R * R] = 1.0
-    rho = 1.0 + 1e-3 * rng.uniform(-1, 1, N)
-    u = 1e-3 * rng.uniform(-1, 1, (D, N))
-    return rho, u, phi
-
-
-CASES = {
-    # name: (lattice, shape, tau, steps, bc, sigma, beta)
-    "d3q19_periodic_ragged": (19, (37, 24, 20), 1.0, 300, (0, 0, 0), 0.03, 0.7),
-    "d3q19_walls_z": (19, (64, 16, 18), 0.8, 300, (0, 0, 1), 0.02, 0.6),
-    "d3q19_walls_xyz": (19, (20, 14, 12), 0.9, 200, (1, 1, 1), 0.03, 0.7),
-    "d3q19_two_segments": (19, (300, 6, 5), 1.0, 150, (0, 0, 0), 0.03, 0.7),
-    "d2q9_periodic": (9, (96, 80, 1), 1.0, 500, (0, 0, 0), 0.03, 0.7),
-    "d2q9_walls_xy": (9, (67, 45, 1), 0.7, 300, (1, 1, 0), 0.02, 0.5),
-}
+    return sharp_state(lattice, shape, seed)
 
 
 @functools.lru_cache(maxsize=None)
@@ -88,26 +74,17 @@ def test_two_species_fp32_matches_oracle(name):
     e_u = max_rel(got["u"], ref["u"])
     e_rho = np.abs(got["rho"] - ref["rho"]).max()
     e_abs = np.abs(got["u"] - ref["u"]).max()
+    fl = _FLOOR["cases"][name]
     print(f"{name} fp32: |dphi| {e_phi:.2e} max-rel u {e_u:.2e} (max |u| "
-          f"{np.abs(ref['u']).max():.1e}, |du| {e_abs:.2e}) |drho| {e_rho:.2e}")
-    assert e_phi < 1e-4 and e_rho < 1e-5 and e_u <= 1e-4
-
-
-FLOW_CASES = {
-    # name: (lattice, shape, tau, steps, sigma, beta): periodic, Taylor-Green u0 0.02
-    "d3q19_tg_droplets": (19, (48, 32, 32), 0.55, 1000, 0.03, 0.7),
-    "d2q9_tg_droplets": (9, (128, 96, 1), 0.8, 1000, 0.03, 0.7),
-}
+          f"{np.abs(ref['u']).max():.1e}, |du| {e_abs:.2e}) |drho| {e_rho:.2e}; "
+          f"float32 floor u {fl['u_max_rel']:.2e} phi {fl['phi_max_abs']:.2e} "
+          f"(ratio {e_u / fl['u_max_rel']:.2f})")
+    assert e_u <= max(1e-5, 2 * fl["u_max_rel"])
+    assert e_phi <= max(1e-5, 2 * fl["phi_max_abs"]) and e_rho < 1e-5
 
 
 def _flow_state(lattice, shape):
-    nx, ny, nz = shape
-    _, _, phi = _state(lattice, shape, 5)
-    if lattice == 9:
-        rho, u = inputs.taylor_green_2d(nx, ny, 0.02)
-    else:
-        rho, u = inputs.taylor_green_3d(nx, ny, nz, 0.02)
-    return rho, u, phi
+    return flow_state(lattice, shape)
 
 
 @pytest.mark.parametrize("name", sorted(FLOW_CASES))
@@ -122,22 +99,26 @@ def test_two_species_in_a_flow_fp32(name):
     got = run(p, rho, u, steps, phi=phi, phi_out=True)
     e_u = max_rel(got["u"], ref["u"])
     e_phi = np.abs(got["phi"] - ref["phi"]).max()
+    fl = _FLOOR["flow_cases"][name]
     print(f"{name} fp32: max-rel u {e_u:.2e} (max |u| {np.abs(ref['u']).max():.1e}), "
-          f"|dphi| {e_phi:.2e}")
-    assert e_u <= 5e-5 and e_phi < 1e-4
+          f"|dphi| {e_phi:.2e}; float32 floor u {fl['u_max_rel']:.2e} "
+          f"phi {fl['phi_max_abs']:.2e}")
+    assert e_u <= max(1e-5, 2 * fl["u_max_rel"])
+    assert e_phi <= max(1e-5, 2 * fl["phi_max_abs"])
 
 
 def test_two_species_conservation():
-    lattice, shape = 19, (48, 20, 16)
+    lattice, shape, tau, steps, sigma, beta = CONSERVATION
     rho, u, phi = _state(lattice, shape, 9)
     N = shape[0] * shape[1] * shape[2]
+    floor = _FLOOR["conservation"]
     for storage in ("f32", "f64"):
-        p = make_params(lattice=19, shape=shape, tau=1.0, storage=storage, species=2,
-                        sigma=0.03, beta=0.7)
+        p = make_params(lattice=lattice, shape=shape, tau=tau, storage=storage, species=2,
+                        sigma=sigma, beta=beta)
         with Simulation(p) as sim:
             sim.init(rho, u, phi)
             c0 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
-            sim.step(300)
+            sim.step(steps)
             c1 = sim.moments(rho=False, u=False, pineq=False)["conserved"]
         red0 = (rho * (1 + phi) / 2).sum()
         assert abs(c0[4] - red0) / N < 1e-7
@@ -147,11 +128,15 @@ def test_two_species_conservation():
         if storage == "f64":
             assert max(drift) < 1e-13
         else:
-            # the mixture is stored shifted: total mass to rounding;
-            # the red set is stored unshifted in FP32 (values 0.03-0.33), whose
-            # rounding acts coherently in the near-steady bulk
+            # the mixture is stored shifted: total mass to rounding.  The
+            # species masses move with the rounding of the colour split at
+            # interface nodes (the pure phases store exact zeros); a plain
+            # float32 transcription of the step drifts by the recorded floor
+            print(f"float32 transcription: red {floor['red_drift_per_node']:.2e}, "
+                  f"blue {floor['blue_drift_per_node']:.2e}")
             assert drift[0] < 1e-9
-            assert drift[1] < 1e-6 and drift[2] < 1e-6
+            assert drift[1] <= floor["red_drift_per_node"]
+            assert drift[2] <= floor["red_drift_per_node"]
         np.testing.assert_allclose(c1[1:4], c0[1:4], rtol=0, atol=N * (1e-8 if storage == "f32" else 1e-14))
 
 
