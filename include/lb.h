@@ -152,7 +152,9 @@ size_t lb_required_bytes(const lb_params* p);
 /* Validate parameters without touching the device. */
 int lb_validate(const lb_params* p);
 
-/* Create a simulation on the current HIP device.
+/* Create a simulation on the current HIP device: the single population set
+ * per species and the moment arrays the method needs (Section 4 counts the
+ * arrays per node; Section 3: no second population set).
  *   dev_mem    device buffer of dev_bytes >= lb_required_bytes(p), 256-byte
  *              aligned, owned by the caller and outliving the handle; or
  *              NULL, in which case the library allocates (hipMalloc) and
@@ -216,7 +218,10 @@ int lb_synchronize(lb_handle* h);
  * batch's stream.  Not while a call on the handle is in progress. */
 int lb_set_stream(lb_handle* h, void* hip_stream);
 
-/* Read the moments of the current populations (blocks until done).
+/* Read the moments of the current populations (blocks until done): the
+ * density, velocity and non-equilibrium stress of Section 2's moment
+ * definitions (Pi^neq as in Section 4's moment computation), copied out to
+ * the host.
  *   rho[N]      density (rho0 + deviation), or NULL
  *   u[D*N]      velocity u = (j + F/2)/rho0, or NULL
  *   pineq[K*N]  non-equilibrium stress, K = D(D+1)/2, or NULL
@@ -233,7 +238,8 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
 /* Number of completed time steps since lb_init. */
 int64_t lb_step_count(const lb_handle* h);
 
-/* Destroy a handle (frees library-owned memory).  NULL is accepted. */
+/* Destroy a handle (frees library-owned memory; a caller-owned buffer is
+ * left to the caller).  NULL is accepted.  Waits for the handle's stream. */
 int lb_destroy(lb_handle* h);
 
 /* Static description of a status code.  Never NULL. */
