@@ -124,13 +124,16 @@ def _blocked_bytes(Q, M, NS, ssize, csize, species=1):
     """Footprint of the documented blocked layout over NS storage nodes:
     block B = 32 KiB of population storage (at least 1024 nodes, at most the
     next power of two >= NS), node count padded to a multiple of B, each
-    region 256-byte aligned, plus 64 KiB of FP64 reduction partials."""
+    region 256-byte aligned, plus (two species) one reference-colour byte per
+    padded node, plus 64 KiB of FP64 reduction partials."""
     B = 1024
     while B < NS and B * ssize < 32768:
         B *= 2
     npad = -(-NS // B) * B
     al = lambda v: -(-v // 256) * 256
-    return al(species * Q * npad * ssize) + al(M * npad * csize) + al(1024 * 8 * 8), B, npad
+    ref = al(npad) if species == 2 else 0
+    return (al(species * Q * npad * ssize) + al(M * npad * csize) + ref + al(1024 * 8 * 8), B,
+            npad)
 
 
 def test_required_bytes_of_ragged_domains():
