@@ -141,14 +141,23 @@ def serving(torch, jobs: int, rate: float, budget_gb: float, overlap: bool = Tru
 
     specs = poisson_mix(jobs, rate=rate, seed=2026)
     side = torch.cuda.Stream()
+    last = [time.perf_counter()]
+
+    def progress(c):
+        # one line on stderr every 20 s of a long serving run
+        if time.perf_counter() - last[0] >= 20.0:
+            last[0] = time.perf_counter()
+            print(f"serving {jobs} requests at {rate}/s: t {c['t']:.0f} s, chunk {c['chunks']}, "
+                  f"active {c['active']}, finished {c['finished']}", file=sys.stderr, flush=True)
+
     with torch.cuda.stream(side):
         be = GpuBackend()
         rep = Server(be, hbm_budget=int(budget_gb * 1e9), chunk_steps=200,
-                     overlap=overlap).run(specs)
+                     overlap=overlap, progress=progress).run(specs)
         be.close()
     torch.cuda.synchronize()
     s = rep.summary()
-    s.update({"rate_per_s": rate, "budget_GB": budget_gb, "overlap": overlap,
+    s.update({"requests": jobs, "rate_per_s": rate, "budget_GB": budget_gb, "overlap": overlap,
               "mix": "D2Q9/D3Q19 x TG/channel x f32/f16s, edge 64..256 log-uniform, "
                      "200-2000 steps, seeded Poisson arrivals"})
     return s

@@ -263,11 +263,22 @@ int lb_batch_create(void* hip_stream, lb_batch** out);
  * drops out of later launches.  Each handle's result is bitwise the same as
  * when it is stepped in a batch of its own.  Runs of >= 3 steps with a fixed
  * set of handles are captured once as a HIP graph and replayed (unless
- * disabled with lb_batch_set_graphs); the call returns after the graph
- * replays complete.  The descriptor tables live in device and pinned host
+ * disabled with lb_batch_set_graphs); the instantiated graphs of the last
+ * 16 launch configurations are kept and reused by later calls that launch
+ * the same configuration; the call returns after the graph replays
+ * complete.  The descriptor tables live in device and pinned host
  * buffers owned by the batch, grown on demand.  LB_EINVAL for NULL or
  * duplicate handles, negative counts, or a handle on another stream. */
 int lb_batch_step(lb_batch* b, lb_handle* const* handles, const int64_t* nsteps, int count);
+
+/* FP64 conservation sums of several handles of this batch's stream in one
+ * round trip: out[6 i .. 6 i + 5] = total mass, momentum j (3), red mass,
+ * blue mass of handles[i], as lb_moments' conserved[] (a serving loop calls
+ * it between chunks to stop a simulation whose state has blown up).  Waits
+ * for the stream.  LB_ENONFINITE (after filling every output) if any
+ * handle's mass or momentum is not finite; LB_EINVAL for a NULL or foreign
+ * handle.  The pinned staging is owned by the batch, grown on demand. */
+int lb_batch_conserved(lb_batch* b, lb_handle* const* handles, int count, double* out);
 
 /* Enable (default) or disable graph capture of batched step runs. */
 int lb_batch_set_graphs(lb_batch* b, int enable);

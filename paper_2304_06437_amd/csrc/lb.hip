@@ -252,6 +252,25 @@ void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) 
 
 int launch_status(hipError_t e) { return status_of(e); }
 
+// Host side of the FP64 conservation reduction: sum the per-block partial
+// sums into [mass, j (3), red mass, blue mass]; LB_ENONFINITE if the mass or
+// momentum is not finite (the outputs are filled either way).
+int finish_conserved(const lb_handle* h, const double* part, double* out) {
+  const bool two = h->p.species == 2;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int b = 0; b < kRedBlocks; ++b)
+    for (int q = 0; q < 5; ++q) acc[q] += part[(size_t)b * 8 + q];
+  out[0] = (double)h->L.N * h->p.rho0 + acc[0];
+  out[1] = acc[1];
+  out[2] = acc[2];
+  out[3] = acc[3];
+  out[4] = two ? acc[4] : out[0];
+  out[5] = two ? out[0] - acc[4] : 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(out[q])) return LB_ENONFINITE;
+  return LB_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -505,17 +524,7 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
       LB_TRY_HIP(hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, h->stream));
       LB_TRY_HIP(hipStreamSynchronize(h->stream));
-      double acc[5] = {0, 0, 0, 0, 0};
-      for (int b = 0; b < kRedBlocks; ++b)
-        for (int q = 0; q < 5; ++q) acc[q] += part[(size_t)b * 8 + q];
-      conserved[0] = (double)N * h->p.rho0 + acc[0];
-      conserved[1] = acc[1];
-      conserved[2] = acc[2];
-      conserved[3] = acc[3];
-      conserved[4] = two ? acc[4] : conserved[0];
-      conserved[5] = two ? conserved[0] - acc[4] : 0.0;
-      for (int q = 0; q < 4; ++q)
-        if (!std::isfinite(conserved[q])) st = LB_ENONFINITE;
+      st = finish_conserved(h, part.data(), conserved);
     } else {
       LB_TRY_HIP(hipStreamSynchronize(h->stream));
     }
@@ -612,6 +621,14 @@ struct lb_batch {
   hipEvent_t copied = nullptr;
   bool copy_pending = false;
   int graphs = 1;
+  // Instantiated one-step graphs, keyed by the launch configuration they
+  // captured (kernels, table addresses, job and work-unit counts).  The
+  // tables are rewritten before every run, so a graph serves every call
+  // whose segments launch the same configuration, whichever handles it
+  // holds.  Oldest first; cleared when the table buffer moves.
+  std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graph_cache;
+  double* c_buf = nullptr;  // pinned staging of lb_batch_conserved
+  size_t c_cap = 0;
 };
 
 namespace {
@@ -628,6 +645,28 @@ struct BatchSegment {
   int64_t steps = 0;
   std::vector<BatchGroup> groups;
 };
+
+constexpr size_t kGraphCacheSize = 16;
+
+std::vector<int64_t> graph_key(const lb_batch* b, const BatchSegment& seg) {
+  std::vector<int64_t> k;
+  k.push_back((int64_t)(intptr_t)b->d_buf);
+  for (const auto& g : seg.groups) {
+    k.push_back((int64_t)(intptr_t)g.impl);
+    k.push_back(g.v2);
+    k.push_back((int64_t)g.jobs.size());
+    k.push_back((int64_t)g.off_k1);
+    k.push_back((int64_t)g.off_k2);
+    k.push_back(g.units_k1);
+    k.push_back(g.units_k2);
+  }
+  return k;
+}
+
+void clear_graph_cache(lb_batch* b) {
+  for (auto& e : b->graph_cache) (void)hipGraphExecDestroy(e.second);
+  b->graph_cache.clear();
+}
 
 hipError_t launch_segment_step(const lb_batch* b, const BatchSegment& seg) {
   for (const auto& g : seg.groups) {
@@ -738,6 +777,7 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
     }
     if (bytes > b->d_cap) {
       LB_TRY_HIP(hipStreamSynchronize(b->stream));  // old tables may still be in use
+      clear_graph_cache(b);  // the cached graphs point into the old tables
       if (b->d_buf) (void)hipFree(b->d_buf);
       b->d_buf = nullptr;
       b->d_cap = 0;
@@ -763,25 +803,31 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
     for (const auto& seg : segs) {
       const bool graph = b->graphs && b->stream != nullptr && seg.steps >= 3;
       if (graph) {
-        hipGraph_t gr = nullptr;
+        const std::vector<int64_t> key = graph_key(b, seg);
         hipGraphExec_t ex = nullptr;
-        LB_TRY_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
-        hipError_t le = launch_segment_step(b, seg);
-        hipError_t ce = hipStreamEndCapture(b->stream, &gr);
-        if (le != hipSuccess || ce != hipSuccess) {
-          if (gr) (void)hipGraphDestroy(gr);
-          return status_of(le != hipSuccess ? le : ce);
-        }
-        hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
+        for (const auto& e : b->graph_cache)
+          if (e.first == key) ex = e.second;
+        if (!ex) {
+          hipGraph_t gr = nullptr;
+          LB_TRY_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+          hipError_t le = launch_segment_step(b, seg);
+          hipError_t ce = hipStreamEndCapture(b->stream, &gr);
+          if (le != hipSuccess || ce != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return status_of(le != hipSuccess ? le : ce);
+          }
+          hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
           (void)hipGraphDestroy(gr);
-          return status_of(ie);
+          if (ie != hipSuccess) return status_of(ie);
+          if (b->graph_cache.size() >= kGraphCacheSize) {
+            (void)hipGraphExecDestroy(b->graph_cache.front().second);
+            b->graph_cache.erase(b->graph_cache.begin());
+          }
+          b->graph_cache.emplace_back(key, ex);
         }
         hipError_t ge = hipSuccess;
         for (int64_t s = 0; s < seg.steps && ge == hipSuccess; ++s) ge = hipGraphLaunch(ex, b->stream);
         hipError_t se = hipStreamSynchronize(b->stream);
-        (void)hipGraphExecDestroy(ex);
-        (void)hipGraphDestroy(gr);
         if (ge != hipSuccess) return status_of(ge);
         if (se != hipSuccess) return status_of(se);
       } else {
@@ -807,11 +853,41 @@ int lb_step_batch(lb_handle* const* hs, const int64_t* nsteps, int count) {
   return st != LB_OK ? st : dst;
 }
 
+int lb_batch_conserved(lb_batch* b, lb_handle* const* hs, int count, double* out) {
+  if (!b || count < 0 || (count > 0 && (!hs || !out))) return LB_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!hs[i] || hs[i]->stream != b->stream) return LB_EINVAL;
+  if (count == 0) return LB_OK;
+  const size_t per = (size_t)kRedBlocks * 8;  // doubles of one handle's partial sums
+  const size_t need = per * (size_t)count * sizeof(double);
+  if (need > b->c_cap) {
+    LB_TRY_HIP(hipStreamSynchronize(b->stream));
+    if (b->c_buf) (void)hipHostFree(b->c_buf);
+    b->c_buf = nullptr;
+    b->c_cap = 0;
+    LB_TRY_HIP(hipHostMalloc((void**)&b->c_buf, need, hipHostMallocDefault));
+    b->c_cap = need;
+  }
+  for (int i = 0; i < count; ++i) {
+    LB_TRY_HIP(hs[i]->impl->conserved(hs[i]));
+    LB_TRY_HIP(hipMemcpyAsync(b->c_buf + per * i, hs[i]->partial, per * sizeof(double),
+                              hipMemcpyDeviceToHost, b->stream));
+  }
+  LB_TRY_HIP(hipStreamSynchronize(b->stream));
+  int st = LB_OK;
+  for (int i = 0; i < count; ++i)
+    if (finish_conserved(hs[i], b->c_buf + per * i, out + 6 * (size_t)i) != LB_OK)
+      st = LB_ENONFINITE;
+  return st;
+}
+
 int lb_batch_destroy(lb_batch* b) {
   if (!b) return LB_OK;
   int st = LB_OK;
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) st = status_of(e);
+  clear_graph_cache(b);
+  if (b->c_buf) (void)hipHostFree(b->c_buf);
   if (b->d_buf) (void)hipFree(b->d_buf);
   if (b->h_buf) (void)hipHostFree(b->h_buf);
   if (b->copied) (void)hipEventDestroy(b->copied);

@@ -119,6 +119,8 @@ def load():
     lib.lb_batch_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     lib.lb_batch_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.lb_batch_conserved.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.c_int, dp]
     lib.lb_batch_destroy.argtypes = [ctypes.c_void_p]
     _lib = lib
     return lib
@@ -305,6 +307,19 @@ def lb_step_batch_noalloc(handles, nsteps):
     hs = (ctypes.c_void_p * max(n, 1))(*[h.value for h in handles])
     ns = (ctypes.c_int64 * max(n, 1))(*[int(k) for k in nsteps])
     _check(load().lb_step_batch_noalloc(hs, ns, n), "lb_step_batch_noalloc")
+
+
+def lb_batch_conserved(b, handles):
+    """FP64 conservation sums of several handles in one round trip:
+    (array[count, 6] of mass, j (3), red mass, blue mass; status), status
+    LB_ENONFINITE when some row is not finite."""
+    n = len(handles)
+    out = np.empty((max(n, 1), 6))
+    hs = (ctypes.c_void_p * max(n, 1))(*[h.value for h in handles])
+    st = load().lb_batch_conserved(b, hs, n, _dptr(out))
+    if st not in (LB_OK, LB_ENONFINITE):
+        _check(st, "lb_batch_conserved")
+    return out[:n], st
 
 
 def lb_batch_set_graphs(b, enable: bool):

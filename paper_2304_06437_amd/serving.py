@@ -50,6 +50,7 @@ class JobSpec:
     flow: str = "tg"              # "tg" (Taylor-Green) or "channel"
     tau: float = 0.6
     arrival: float = 0.0          # seconds after the start of the run
+    amplitude: float = 0.01       # Taylor-Green velocity amplitude u0
 
     @property
     def nodes(self) -> int:
@@ -61,8 +62,8 @@ class JobSpec:
         D = 2 if self.lattice == 9 else 3
         if self.flow == "tg":
             if D == 2:
-                return inputs.taylor_green_2d(nx, ny, 0.01)
-            return inputs.taylor_green_3d(nx, ny, nz, 0.01)
+                return inputs.taylor_green_2d(nx, ny, self.amplitude)
+            return inputs.taylor_green_3d(nx, ny, nz, self.amplitude)
         if self.flow == "channel":
             return inputs.channel_noise(nx, ny, nz, D, seed=12345 + self.job_id)
         raise ValueError(self.flow)
@@ -202,6 +203,16 @@ class GpuBackend:
     def step(self, handles, nsteps):
         self.lb.lb_batch_step(self.batch, [s.handle for s in handles], nsteps)
 
+    def blown_up(self, handles) -> list:
+        """Indices of the simulations whose mass or momentum (FP64 device
+        reduction, one round trip for all) is no longer finite."""
+        if not handles:
+            return []
+        sums, st = self.lb.lb_batch_conserved(self.batch, [s.handle for s in handles])
+        if st == self.lb.LB_OK:
+            return []
+        return [i for i in range(len(handles)) if not np.isfinite(sums[i, :4]).all()]
+
     def chunk_done(self):
         """Order the side stream after everything enqueued on the batch's
         stream so far.  Called by the main thread between batch steps, when
@@ -234,9 +245,19 @@ class GpuBackend:
 
 
 class Server:
+    """check_finite: after every chunk, stop the simulations whose state is
+    no longer finite (marked failed at that chunk, memory released), using
+    the backend's blown_up() when it has one.  progress: optional callable
+    taking a dict of counters (time, chunks, active, finished), called after
+    every chunk."""
+
     def __init__(self, backend, hbm_budget: int, chunk_steps: int = 200,
                  max_active: int = 256, keep_moments: bool = False, clock=time.perf_counter,
-                 sleep=time.sleep, overlap: bool = False):
+                 sleep=time.sleep, overlap: bool = False, check_finite: bool = True,
+                 progress=None):
+        self.check_finite = check_finite
+        # progress(dict): called after every chunk with the run's counters
+        self.progress = progress
         self.backend = backend
         self.budget = int(hbm_budget)
         self.chunk = int(chunk_steps)
@@ -395,6 +416,21 @@ class Server:
                     active = []
                     continue
                 chunks += 1
+                if self.progress is not None:
+                    self.progress({"t": now(), "chunks": chunks, "active": len(active),
+                                   "finished": len(results)})
+                kept, failed = self._blown_up(active, nsteps)
+                for a, done in failed:
+                    a.result.status = "failed"
+                    a.result.error = f"non-finite state within {done} steps"
+                    a.result.finished = now()
+                    results[a.spec.job_id] = a.result
+                    self._release(a)
+                    used -= a.nbytes
+                if failed:
+                    keep = {id(a) for a in kept}
+                    nsteps = [k for a, k in zip(active, nsteps) if id(a) in keep]
+                    active = kept
                 still = []
                 for a, k in zip(active, nsteps):
                     a.remaining -= k
@@ -491,6 +527,21 @@ class Server:
                 active = []
                 continue
             chunks += 1
+            if self.progress is not None:
+                self.progress({"t": now(), "chunks": chunks, "active": len(active),
+                               "finished": len(results)})
+            kept, failed = self._blown_up(active, nsteps)
+            for a, done in failed:
+                a.result.status = "failed"
+                a.result.error = f"non-finite state within {done} steps"
+                a.result.finished = now()
+                results[a.spec.job_id] = a.result
+                self._release(a)
+                used -= a.nbytes
+            if failed:
+                keep = {id(a) for a in kept}
+                nsteps = [k for a, k in zip(active, nsteps) if id(a) in keep]
+                active = kept
             still = []
             for a, k in zip(active, nsteps):
                 a.remaining -= k
@@ -514,6 +565,22 @@ class Server:
             active = still
         ordered = [results[s.job_id] for s in sorted(specs, key=lambda s: s.job_id)]
         return ServeReport(ordered, now(), max_active, peak, chunks, phase)
+
+    def _blown_up(self, active, stepped_now):
+        """Jobs of `active` (each advanced by stepped_now[i] this chunk) whose
+        state has blown up: returns (kept, failed), failed as (job, steps
+        done so far)."""
+        probe = getattr(self.backend, "blown_up", None)
+        if not self.check_finite or probe is None or not active:
+            return active, []
+        bad = set(probe([a.handle for a in active]))
+        kept, failed = [], []
+        for i, a in enumerate(active):
+            if i in bad:
+                failed.append((a, a.spec.steps - a.remaining + stepped_now[i]))
+            else:
+                kept.append(a)
+        return kept, failed
 
     def _release(self, a):
         try:

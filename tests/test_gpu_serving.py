@@ -147,3 +147,74 @@ def test_one_shot_step_batch_equals_batch_object():
     for a, b in zip(got, ref):
         for k in ("rho", "u", "pineq"):
             assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_blown_up_job_fails_at_the_next_chunk(overlap):
+    """A request whose state blows up (Taylor-Green u0 0.5 at tau 0.501 goes
+    non-finite within ~50 steps) is stopped by the per-chunk FP64 check after
+    its first chunk and its memory released; every other request in the mix
+    completes bit for bit as when run alone."""
+    import torch
+
+    stable = [JobSpec(i, s.lattice, s.shape, s.steps, storage=s.storage, flow=s.flow)
+              for i, s in enumerate(MIX[:4])]
+    bad = JobSpec(4, 9, (64, 64, 1), 1000, storage="f32", flow="tg", tau=0.501, amplitude=0.5)
+    specs = stable + [bad]
+    with torch.cuda.stream(_stream()):
+        be = GpuBackend(keep_moments=True)
+        rep = Server(be, hbm_budget=10 ** 11, chunk_steps=100, keep_moments=True,
+                     overlap=overlap).run(specs)
+        be.close()
+    r = {x.job_id: x for x in rep.results}
+    assert r[4].status == "failed" and "within 100 steps" in r[4].error, r[4]
+    for s in stable:
+        assert r[s.job_id].status == "done", r[s.job_id]
+        alone = _batch_run([s])[0]
+        assert np.array_equal(r[s.job_id].moments["u"], alone["u"]), s.job_id
+
+
+def test_batch_conserved_matches_lb_moments():
+    import torch
+
+    with torch.cuda.stream(_stream()):
+        sims = [_sim(s) for s in MIX[:3]]
+        b = lb.lb_batch_create(torch.cuda.current_stream().cuda_stream)
+        lb.lb_batch_step(b, [s.handle for s in sims], [7, 3, 5])
+        sums, st = lb.lb_batch_conserved(b, [s.handle for s in sims])
+        assert st == lb.LB_OK
+        for i, sim in enumerate(sims):
+            c = sim.moments(rho=False, u=False, pineq=False)["conserved"]
+            assert np.array_equal(sums[i], c), i
+        lb.lb_batch_destroy(b)
+        for sim in sims:
+            sim.close()
+
+
+def test_graph_cache_reuses_graphs_across_calls():
+    """Consecutive calls with the same launch configuration replay the cached
+    graph; results equal direct launches bit for bit over several calls."""
+    import torch
+
+    specs = MIX[:3]
+    with torch.cuda.stream(_stream()):
+        a = [_sim(s) for s in specs]
+        c = [_sim(s) for s in specs]
+        ba = lb.lb_batch_create(torch.cuda.current_stream().cuda_stream)
+        bc = lb.lb_batch_create(torch.cuda.current_stream().cuda_stream)
+        lb.lb_batch_set_graphs(bc, False)
+        for _ in range(4):  # same configuration each call
+            lb.lb_batch_step(ba, [s.handle for s in a], [20, 20, 20])
+            lb.lb_batch_step(bc, [s.handle for s in c], [20, 20, 20])
+        lb.lb_batch_step(ba, [s.handle for s in a[:2]], [9, 9])  # another configuration
+        lb.lb_batch_step(bc, [s.handle for s in c[:2]], [9, 9])
+        lb.lb_batch_step(ba, [s.handle for s in a], [6, 6, 6])  # back to the first
+        lb.lb_batch_step(bc, [s.handle for s in c], [6, 6, 6])
+        for x, y in zip(a, c):
+            mx, my = x.moments(phi=False), y.moments(phi=False)
+            for k in ("rho", "u", "pineq"):
+                assert np.array_equal(mx[k], my[k]), k
+        lb.lb_batch_destroy(ba)
+        lb.lb_batch_destroy(bc)
+        for s in a + c:
+            s.close()

@@ -265,3 +265,48 @@ def test_result_in_a_mix_equals_result_alone():
         assert r.status == alone.status == "done"
         for k in ("rho", "u", "pineq"):
             assert np.array_equal(r.moments[k], alone.moments[k])
+
+
+class BlowUpBackend(CountingBackend):
+    """Job `bad` blows up after `at` steps; blown_up() reports it from then on."""
+
+    def __init__(self, clock, bad, at, **kw):
+        super().__init__(clock, **kw)
+        self.bad, self.at = bad, at
+        self.done = {}
+        self.stepped_after_failure = 0
+
+    def step(self, handles, nsteps):
+        super().step(handles, nsteps)
+        for h, k in zip(handles, nsteps):
+            if h.job_id == self.bad and self.done.get(h.job_id, 0) >= self.at:
+                self.stepped_after_failure += 1
+            self.done[h.job_id] = self.done.get(h.job_id, 0) + k
+
+    def blown_up(self, handles):
+        return [i for i, h in enumerate(handles)
+                if h.job_id == self.bad and self.done[h.job_id] >= self.at]
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_blown_up_job_fails_at_the_next_chunk_and_frees_its_slot(overlap):
+    clk = FakeClock()
+    be = BlowUpBackend(clk, bad=1, at=130)
+    specs = _specs(4, steps=1000)
+    need = specs[0].nodes * 100
+    rep = Server(be, hbm_budget=int(3.5 * need), chunk_steps=100, clock=clk, sleep=clk.sleep,
+                 overlap=overlap).run(specs)
+    r = {x.job_id: x for x in rep.results}
+    assert r[1].status == "failed" and "within 200 steps" in r[1].error
+    assert be.stepped_after_failure == 0     # never stepped again once detected
+    assert all(r[i].status == "done" for i in (0, 2, 3))
+    assert be.live == 0
+    assert r[1].finished < r[2].finished     # stopped early, not after its 1000 steps
+
+
+def test_blow_up_check_can_be_switched_off():
+    clk = FakeClock()
+    be = BlowUpBackend(clk, bad=0, at=50)
+    rep = Server(be, hbm_budget=10 ** 12, chunk_steps=100, clock=clk, sleep=clk.sleep,
+                 check_finite=False).run(_specs(1, steps=300))
+    assert rep.results[0].status == "done"
