@@ -189,6 +189,16 @@ int lb_sweep(lb_handle* h, int which);
 /* (lb_init and lb_moments use the moment arrays as staging for their host
  * transfers: after them, run which = 0 before a which = 1 sweep.) */
 
+/* Order in which the stream-collide sweep's wavefronts take their row
+ * segments, for testing that the sweep's result does not depend on the
+ * order its parallel work runs in (the thread-safety of Section 3): 0 the
+ * natural order (default), 1 reversed, 2 a strided permutation that sends
+ * neighbouring wavefronts to distant rows.  Results are bitwise the same
+ * for every order.  Batched execution always uses the natural order.
+ * LB_EINVAL for another value; LB_EUNSUPPORTED for orders 1 and 2 on a
+ * domain of 2^31 or more row segments. */
+int lb_set_sweep_order(lb_handle* h, int order);
+
 /* Device layout of the handle's state, for tests and tools.  The population
  * region (species*Q arrays of the storage type: set 0 then set 1) starts at
  * byte pop_offset of the device buffer, the moment region (M arrays of the

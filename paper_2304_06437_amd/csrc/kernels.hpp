@@ -55,7 +55,12 @@ struct StepParams {
   // the low (side 0) or high (side 1) face of an axis; moving != 0 if any
   // is non-zero.
   int32_t moving;
-  int32_t pad2_;
+  // Order in which a sweep's work units (wavefronts of stream-collide) are
+  // mapped to row segments: 0 the natural one; otherwise unit u of U takes
+  // segment (u * order_mul) mod U, a permutation (gcd(order_mul, U) = 1);
+  // order_mul = U - 1 gives the reversed order.  For tests of the sweep's
+  // independence of execution order.
+  int32_t order_mul;
   C wall[6][3];
 };
 
@@ -674,12 +679,22 @@ struct StreamCollide {
   }
 };
 
+// Unit u of U under the order permutation of StepParams::order_mul (units
+// past U stay past U).  The host sets order_mul only for U < 2^32, so the
+// product fits 64 bits.
+template <typename C>
+__device__ __forceinline__ int64_t ordered_unit(const StepParams<C>& p, int64_t u, int64_t U) {
+  if (p.order_mul == 0 || u >= U) return u;
+  return (int64_t)(((uint64_t)u * (uint64_t)(uint32_t)p.order_mul) % (uint64_t)U);
+}
+
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false,
           bool PAD = true>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  StreamCollide<L, ORDER, S, C, E, H, FD, PAD>::run_wave(
-      m, f, p, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int64_t w = flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  StreamCollide<L, ORDER, S, C, E, H, FD, PAD>::run_wave(m, f, p,
+                                                         ordered_unit(p, w, p.nseg * p.ny * p.nz));
 }
 
 // -------------------------------------------------------------------------

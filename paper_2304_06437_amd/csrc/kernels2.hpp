@@ -779,8 +779,9 @@ __global__ __launch_bounds__(256) void k_stream_collide2(const C* __restrict__ m
                                                          ColourParams<C> cp,
                                                          const unsigned char* __restrict__ flag,
                                                          NciParams<C> q) {
+  const int64_t w = flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
   StreamCollide2<L, S, C, E, WHOLE, NCI>::run_wave(
-      m, f, p, cp, flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6), flag, q);
+      m, f, p, cp, ordered_unit(p, w, p.nseg * p.ny * p.nz), flag, q);
 }
 
 // Initialisation: set 0 = f^eq - t rho0; red f_R = (1 + phi)/2 f^eq stored

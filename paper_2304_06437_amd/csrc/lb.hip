@@ -240,7 +240,7 @@ void fill_params(StepParams<C>& q, const lb_params* p, const Layout& L, int v2) 
   // moving walls, prescaled like the momentum coefficient: -6 rho0 u_w / wden
   const double wden = p->lattice == LB_D3Q27 ? 216.0 : 36.0;
   q.moving = 0;
-  q.pad2_ = 0;
+  q.order_mul = 0;
   for (int a = 0; a < 3; ++a)
     for (int side = 0; side < 2; ++side)
       for (int b = 0; b < 3; ++b) {
@@ -451,6 +451,26 @@ int lb_sweep(lb_handle* h, int which) {
     LB_TRY_HIP(h->impl->stream_collide(h));
     ++h->steps;
   }
+  return LB_OK;
+}
+
+int lb_set_sweep_order(lb_handle* h, int order) {
+  if (!h || order < 0 || order > 2) return LB_EINVAL;
+  const int64_t U = h->p32.nseg * h->p32.ny * h->p32.nz;  // stream-collide wavefronts
+  int64_t mul = 0;
+  if (order == 1) mul = U - 1;
+  if (order == 2) {
+    // a multiplier near U/phi that shares no factor with U (mixes distant
+    // rows into neighbouring units)
+    mul = (int64_t)(0.6180339887 * (double)U) | 1;
+    auto gcd = [](int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; };
+    while (mul > 1 && gcd(mul, U) != 1) mul += 2;
+    if (mul >= U) mul = U - 1;
+  }
+  if (order != 0 && U >= (int64_t(1) << 31)) return LB_EUNSUPPORTED;
+  if (U <= 1) mul = 0;
+  h->p32.order_mul = (int32_t)mul;
+  h->p64.order_mul = (int32_t)mul;
   return LB_OK;
 }
 

@@ -108,6 +108,7 @@ def load():
     lib.lb_timing_end.argtypes = [H, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.lb_sweep.argtypes = [H, ctypes.c_int]
+    lib.lb_set_sweep_order.argtypes = [H, ctypes.c_int]
     lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
@@ -192,6 +193,12 @@ def lb_step(h, nsteps: int):
 
 def lb_sweep(h, which: int):
     _check(load().lb_sweep(h, int(which)), "lb_sweep")
+
+
+def lb_set_sweep_order(h, order: int):
+    """0 natural, 1 reversed, 2 strided order of the stream-collide
+    sweep's wavefronts (results are bitwise the same)."""
+    _check(load().lb_set_sweep_order(h, int(order)), "lb_set_sweep_order")
 
 
 def lb_layout(h):

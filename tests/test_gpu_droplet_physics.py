@@ -8,11 +8,13 @@ frequency is omega*^2 = m(m-1)(m+1)(m+2) sigma / (R^3 [(m+1) + m]), i.e.
   chi = (2m+1)^2 sqrt(mu1 mu2 rho1 rho2) /
         (2 R [m rho2 + (m+1) rho1] [sqrt(mu1 rho1) + sqrt(mu2 rho2)])
       = 1.25 sqrt(nu)/R  (m = 2, equal fluids).
-The two-species GPU path (D3Q19, FP32) runs the paper's setup at reduced
-size; the interface height on the vertical mid-line is fitted with a damped
-sinusoid.  The period is held within 10 % of the Miller-Scriven value at
-R = 32 (diffuse-interface and finite-resolution effects: measured 1.058 at
-deformation 0.08), and the gap must shrink with resolution (R = 24 -> 40).
+The two-species GPU path (D3Q19, FP32) runs the paper's own setup (360^3,
+R_e 40, sigma 0.03, tau 0.55 and 0.75) with the period taken from two
+subsequent peaks as in the paper, and reduced sizes where the interface
+height on the vertical mid-line is fitted with a damped sinusoid: within
+8 % of the Miller-Scriven value at R = 32 (diffuse-interface and
+finite-resolution effects: measured 1.058 at deformation 0.08), and the gap
+must shrink with resolution (R = 24 -> 40).
 """
 import math
 
@@ -20,7 +22,7 @@ import numpy as np
 import pytest
 from scipy.optimize import curve_fit
 
-from paper_2304_06437_amd import inputs
+from paper_2304_06437_amd import inputs, lb
 from paper_2304_06437_amd.sim import Simulation, make_params
 
 pytestmark = pytest.mark.gpu
@@ -87,7 +89,7 @@ def test_second_mode_period_matches_miller_scriven():
     ratio = T / T_ms
     print(f"R 32: T_LB {T:.1f}, Miller-Scriven {T_ms:.1f}, ratio {ratio:.4f} (fit rms {rms:.3f})")
     assert rms < 0.3
-    assert 0.95 <= ratio <= 1.10
+    assert 0.95 <= ratio <= 1.08
 
 
 @pytest.mark.timeout(300)
@@ -100,6 +102,79 @@ def test_period_converges_with_resolution():
         ratios.append(T / T_ms)
     print(f"T_LB / T_MS: R 24 {ratios[0]:.4f}, R 40 {ratios[1]:.4f}")
     assert abs(ratios[1] - 1.0) < abs(ratios[0] - 1.0)
+
+
+def midline_history(n, R, delta, tau, steps, every=25):
+    """Upper interface height on the box's vertical mid-line, read every
+    `every` steps straight from the phase-field moment array (one moments
+    sweep refreshes it; lb_layout gives where it lives), so that a 360^3
+    run does not copy the whole field to the host each time."""
+    import torch
+
+    d = 1.0 + delta
+    rho, u, phi = inputs.ellipsoid_droplet(n, (R * d, R * d, R / d ** 2))
+    p = make_params(lattice=19, shape=(n, n, n), tau=tau, storage="f32", species=2,
+                    sigma=SIGMA, beta=BETA)
+    ic, c = n // 2, (n - 1) / 2.0
+    ts, zs = [], []
+    with Simulation(p) as sim:
+        sim.init(rho, u, phi)
+        del rho, u, phi
+        _, mom_off, B, npad, px = lb.lb_layout(sim.handle)
+        M1 = 11  # drho, j (3), Pi^neq (6), phi
+        mom = sim.buffer[mom_off:mom_off + M1 * npad * 4].view(torch.float32)
+        z = np.arange(n)
+        idx = []
+        for xx, yy in ((ic, ic), (ic - 1, ic - 1)):
+            nn = xx + px * (yy + n * z)
+            idx.append(torch.as_tensor((nn // B) * M1 * B + 10 * B + nn % B, device="cuda"))
+        for k in range(steps // every + 1):
+            if k:
+                sim.step(every)
+            lb.lb_sweep(sim.handle, 0)
+            sim.synchronize()
+            line = (0.5 * (mom[idx[0]].double() + mom[idx[1]].double())).cpu().numpy()
+            up = line[ic:]
+            j = int(np.nonzero(up < 0)[0][0])
+            ts.append(k * every)
+            zs.append(ic + j - 1 + up[j - 1] / (up[j - 1] - up[j]) - c)
+    return np.array(ts, dtype=np.float64), np.array(zs)
+
+
+def peak_spacing(ts, zs, skip=200):
+    """Time between the first two maxima (above the signal's mean) of the
+    sampled signal after `skip`, each refined by a parabola through three
+    samples: the paper measures the period from two subsequent peaks."""
+    keep = ts >= skip
+    t, z = ts[keep], zs[keep]
+    mid = z.mean()  # wiggles of the sampled signal near a trough are not peaks
+    peaks = []
+    for i in range(1, len(z) - 1):
+        if z[i] > mid and z[i] > z[i - 1] and z[i] >= z[i + 1]:
+            a = z[i - 1] - 2 * z[i] + z[i + 1]
+            peaks.append(t[i] + (0.5 * (z[i - 1] - z[i + 1]) / a) * (t[1] - t[0]))
+    assert len(peaks) >= 2, peaks
+    return peaks[1] - peaks[0]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("tau,bar", [(0.55, 0.07), (0.75, 0.10)])
+def test_oscillation_at_the_papers_setup(tau, bar):
+    """Section 5.2's setup: a 360^3 box, equivalent radius 40, sigma 0.03,
+    equal densities and viscosities (deformation 0.1, beta 0.7: readings).
+    The period from two subsequent peaks of the mid-line interface against
+    Miller-Scriven (measured: tau 0.55 4635 vs 4406, +5.2 %; tau 0.65 4944 vs
+    4563, +8.4 %; tau 0.75 5060 vs 4669, +8.4 %; the paper prints T_LB ~ 5400
+    at its "nu" 0.75).  The theory's viscous term is a first-order
+    correction (11.6 % of the frequency at tau 0.75, 5.2 % at 0.55), so the
+    bar is tighter where the correction is small."""
+    R = 40.0
+    T_ms = miller_scriven_period(R, tau)
+    ts, zs = midline_history(360, R, 0.1, tau, 7800)
+    T = peak_spacing(ts, zs)
+    print(f"360^3 R 40 tau {tau}: T_LB {T:.1f} (peak to peak), Miller-Scriven {T_ms:.1f}, "
+          f"ratio {T / T_ms:.4f}")
+    assert abs(T / T_ms - 1.0) <= bar
 
 
 def laplace_ratio(n, R, steps=16000, tau=1.0):
