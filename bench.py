@@ -48,10 +48,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(Q: int, M: int, ssize: int, csize: int):
-    """Bytes per lattice update of (moments, stream-collide)."""
-    k1 = Q * ssize + M * csize
-    k2 = M * csize + Q * ssize
+def algorithmic_bytes(Q: int, M: int, ssize: int, csize: int, ref: int = 0):
+    """Bytes per lattice update of (moments, stream-collide); ref: the
+    reference-colour byte of two species, read by the moments sweep and
+    written by stream-collide."""
+    k1 = Q * ssize + M * csize + ref
+    k2 = M * csize + Q * ssize + ref
     return k1, k2
 
 
@@ -341,7 +343,7 @@ def main():
     Q = w["lattice"]
     D = 2 if Q == 9 else 3
     M = 1 + D + D * (D + 1) // 2 + (1 if w["species"] == 2 else 0)
-    b1, b2 = algorithmic_bytes(Q * w["species"], M, ssize, 4)
+    b1, b2 = algorithmic_bytes(Q * w["species"], M, ssize, 4, ref=1 if w["species"] == 2 else 0)
     avg = [kms[i] / max(klaunch[i], 1) for i in range(2)]
     names = ["moments", "stream_collide"]
     dom = 0 if avg[0] > avg[1] else 1
