@@ -4,18 +4,23 @@
 
 Workload: D3Q19, 512^3 periodic 3D Taylor-Green vortex (u0 = 0.02,
 tau = 0.55, rho0 = 1), FP32 shifted population storage and FP32 arithmetic,
-synthetic seeded input.  A step is the whole hot path: the moments sweep and
-the fused stream-collide sweep (boundaries fused).  The state is resident in
-HBM before the timed region; K steps are timed between two device
-synchronisations.  Prints one JSON line.
+synthetic seeded input.  A step is the whole hot path: every node's moments,
+post-collision populations and streaming (boundaries fused), through the
+path lb_step takes by default: the fused step where the shape allows it
+(one launch that keeps the moments in registers), else the moments sweep
+and the stream-collide sweep.  The state is resident in HBM before the
+timed region; K steps are timed between two device synchronisations.  The
+same handle is then timed on the two-sweep path for comparison.  Prints one
+JSON line.
 
-Roofline: algorithmic bytes per lattice update = Q reads + M writes
-(moments) + M reads + Q writes (stream-collide) = 116 + 116 B for D3Q19 FP32.
-The dominant kernel's achieved bandwidth uses its average launch time from
-HIP events recorded on the launch stream during the timed region.  The HBM
-traffic counters (FETCH_SIZE / WRITE_SIZE) come from separate rocprofv3 runs
-kept under profiles/; they are reported only while the kernel source they
-were taken on is unchanged.
+Roofline: algorithmic bytes per lattice update of the fused step = Q reads
++ Q writes = 152 B for D3Q19 FP32; of the two sweeps = Q reads + M writes
+(moments) + M reads + Q writes (stream-collide) = 116 + 116 B.  The dominant
+kernel's achieved bandwidth uses its average launch time from HIP events
+recorded on the launch stream during the timed region.  The HBM traffic
+counters (FETCH_SIZE / WRITE_SIZE) come from separate rocprofv3 runs kept
+under profiles/; they are reported only while the kernel source they were
+taken on is unchanged.
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM roofline, D3Q19 512^3 FP32; p50/p99 solve latency"
 KERNEL_SOURCES = ["paper_2304_06437_amd/csrc/kernels.hpp", "paper_2304_06437_amd/csrc/lattice.hpp",
-                  "paper_2304_06437_amd/csrc/storage.hpp"]
+                  "paper_2304_06437_amd/csrc/storage.hpp", "paper_2304_06437_amd/csrc/fused.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_d3q19_512_traffic.md")
 
 
@@ -323,32 +328,57 @@ def main():
     sim = Simulation(params)
     sim.init(rho, u, phi)
     del rho, u, phi
-    sim.step(args.warmup)
-    sim.synchronize()
+    path, z_tiles = lb.lb_get_step_path(sim.handle)
+    fused = path == lb.LB_PATH_FUSED
 
-    lb.lb_timing_begin(sim.handle, args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kms, klaunch = lb.lb_timing_end(sim.handle)
-    elapsed = t1 - t0
+    def timed(steps, warmup):
+        sim.step(warmup)
+        sim.synchronize()
+        lb.lb_timing_begin(sim.handle, steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kms, klaunch = lb.lb_timing_end(sim.handle)
+        return t1 - t0, kms, klaunch
+
+    elapsed, kms, klaunch = timed(args.steps, args.warmup)
     check = sim.moments(rho=False, u=False, pineq=False)["conserved"]
-    sim.close()
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    mlups = N * args.steps / elapsed / 1e6
     ssize = {"f32": 4, "f16s": 2, "bf16s": 2}[args.storage]
     Q = w["lattice"]
     D = 2 if Q == 9 else 3
     M = 1 + D + D * (D + 1) // 2 + (1 if w["species"] == 2 else 0)
     b1, b2 = algorithmic_bytes(Q * w["species"], M, ssize, 4, ref=1 if w["species"] == 2 else 0)
+    bf = 2 * Q * ssize  # fused step: Q in, Q out
+    two_sweep = None
+    if fused:
+        # the same state, on the two-sweep path
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_TWO_SWEEP, 0)
+        e2, k2, l2 = timed(args.steps, args.warmup)
+        a2 = [k2[i] / max(l2[i], 1) for i in range(2)]
+        two_sweep = {
+            "value": round(N * args.steps / e2 / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(e2 * 1e3 / args.steps, 4),
+            "bytes_per_update": b1 + b2,
+            "step_GBs": round((b1 + b2) * N / (e2 / args.steps) / 1e9, 1),
+            "kernels": {nm: {"avg_ms": round(a2[i], 4),
+                             "algorithmic_GBs": round(bb * N / (a2[i] * 1e-3) / 1e9, 1)}
+                        for i, (nm, bb) in enumerate((("moments", b1), ("stream_collide", b2)))},
+        }
+    sim.close()
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    mlups = N * args.steps / elapsed / 1e6
     avg = [kms[i] / max(klaunch[i], 1) for i in range(2)]
-    names = ["moments", "stream_collide"]
-    dom = 0 if avg[0] > avg[1] else 1
-    bytes_launch = [b1 * N, b2 * N]
-    achieved = bytes_launch[dom] / (avg[dom] * 1e-3) / 1e9
+    if fused:
+        names, bytes_launch, dom, kidx = ["fused_step"], [bf * N], 0, [1]
+        b_update = bf
+    else:
+        names, bytes_launch, kidx = ["moments", "stream_collide"], [b1 * N, b2 * N], [0, 1]
+        dom = 0 if avg[0] > avg[1] else 1
+        b_update = b1 + b2
+    achieved = bytes_launch[dom] / (avg[kidx[dom]] * 1e-3) / 1e9
     headline = args.workload == "d3q19_tg" and args.storage == "f32" and n == 512
     traffic = read_traffic(names[dom]) if headline else None
 
@@ -369,7 +399,8 @@ def main():
             "workload": w["desc"].format(n=n) + f", {args.storage} population storage, "
                         "f32 arithmetic",
             "name": args.workload, "lattice": f"D{D}Q{Q}", "nodes": N,
-            "storage": args.storage, "compute": "f32", "bytes_per_update": b1 + b2,
+            "storage": args.storage, "compute": "f32", "bytes_per_update": b_update,
+            "path": "fused" if fused else "two_sweep", "z_tiles": z_tiles,
         },
         "roofline": {
             "bound": "hbm",
@@ -382,14 +413,15 @@ def main():
             "bytes_per_launch": bytes_launch[dom],
         },
         "kernels": {
-            names[i]: {"avg_ms": round(avg[i], 4), "launches": klaunch[i],
-                       "algorithmic_GBs": round(bytes_launch[i] / (avg[i] * 1e-3) / 1e9, 1),
-                       "vs_best_copy": (round(bytes_launch[i] / (avg[i] * 1e-3) / 1e9 /
+            names[i]: {"avg_ms": round(avg[kidx[i]], 4), "launches": klaunch[kidx[i]],
+                       "algorithmic_GBs": round(bytes_launch[i] / (avg[kidx[i]] * 1e-3) / 1e9, 1),
+                       "vs_best_copy": (round(bytes_launch[i] / (avg[kidx[i]] * 1e-3) / 1e9 /
                                               copies["best"], 4) if copies else None)}
-            for i in range(2)
+            for i in range(len(names))
         },
-        "step_GBs": round((b1 + b2) * N / (ms_per_step * 1e-3) / 1e9, 1),
-        "step_frac_of_peak": round((b1 + b2) * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_GBs": round(b_update * N / (ms_per_step * 1e-3) / 1e9, 1),
+        "step_frac_of_peak": round(b_update * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "two_sweep": two_sweep,
         "copy_ceilings_GBs": copies,
         "dominant_vs_best_copy": (round(achieved / copies["best"], 4) if copies else None),
         "mass_finite": bool(np.isfinite(check[0])),

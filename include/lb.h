@@ -176,7 +176,10 @@ int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_str
 int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi);
 
 /* Enqueue nsteps >= 0 time steps (moments, then fused stream + collide with
- * boundaries) on the handle's stream and return without waiting. */
+ * boundaries) on the handle's stream and return without waiting.  Each
+ * step runs either as the two sweeps of lb_sweep or, where the shape
+ * allows it, as the fused step (lb_set_step_path), whose result is the
+ * same bit for bit. */
 int lb_step(lb_handle* h, int64_t nsteps);
 
 /* Enqueue one half of a time step: which = 0 the moments sweep (reads the
@@ -198,6 +201,38 @@ int lb_sweep(lb_handle* h, int which);
  * LB_EINVAL for another value; LB_EUNSUPPORTED for orders 1 and 2 on a
  * domain of 2^31 or more row segments. */
 int lb_set_sweep_order(lb_handle* h, int order);
+
+/* Path of lb_step.  The two sweeps (Section 4's moments loop, then the
+ * streaming + collision loop of eq. pushLB) pass every node's moments
+ * through the moment arrays.  The fused step computes the same moments and
+ * post-collision populations, with the same arithmetic, in one launch that
+ * keeps the moments in registers: one wavefront per x-row and run of
+ * z-planes, marching in z, which writes into a neighbouring row only after
+ * that row's wavefront has read it (progress words in device memory), so
+ * the in-place update stays thread-safe in the sense of Section 3.  It
+ * moves Q populations in and out per node (152 B for D3Q19 FP32) instead
+ * of Q + M each way.
+ *   Shapes: one species, D3Q19 or D3Q27, FP32 / FP16 / BF16 storage with
+ *   FP32 arithmetic, nx = 128, 256 or 512 (D3Q27: 128, 256); every tile
+ *   must be resident at once (ny * z_tiles wavefronts), and the device
+ *   must support cooperative launch.
+ *   path: LB_PATH_AUTO (what lb_create sets: fused where the shape allows
+ *   it and its tiles fill at least half the device, else two sweeps),
+ *   LB_PATH_TWO_SWEEP, LB_PATH_FUSED.  z_tiles: runs of planes per row,
+ *   0 to choose (at least 8 planes per run); ignored for two sweeps.
+ * Waits for the handle's stream.  LB_EUNSUPPORTED if LB_PATH_FUSED cannot
+ * run this shape or tiling (the path is then unchanged), LB_EINVAL for a
+ * bad path or z_tiles > nz.  A fused step that waits past its bound gives
+ * up (its result is invalid): the next lb_synchronize, lb_moments or
+ * lb_set_step_path call returns LB_EDEVICE once. */
+#define LB_PATH_AUTO 0
+#define LB_PATH_TWO_SWEEP 1
+#define LB_PATH_FUSED 2
+int lb_set_step_path(lb_handle* h, int path, int64_t z_tiles);
+
+/* The path lb_step takes (LB_PATH_TWO_SWEEP or LB_PATH_FUSED) and, for the
+ * fused step, its runs of planes per row (0 for two sweeps). */
+int lb_get_step_path(const lb_handle* h, int* path, int64_t* z_tiles);
 
 /* Device layout of the handle's state, for tests and tools.  The population
  * region (species*Q arrays of the storage type: set 0 then set 1) starts at
@@ -339,7 +374,8 @@ int lb_timing_begin(lb_handle* h, int64_t max_steps);
 
 /* Stop timing (synchronises the stream) and report the summed device time
  * and launch count of the moments kernel (index 0) and the stream-collide
- * kernel (index 1).  ms[2], launches[2]. */
+ * kernel (index 1).  ms[2], launches[2].  Steps taken by the fused step
+ * report its kernel at index 1 and no time at index 0. */
 int lb_timing_end(lb_handle* h, double* ms, int64_t* launches);
 
 /* Plain device-to-device copy kernel (bytes a multiple of 16, both pointers

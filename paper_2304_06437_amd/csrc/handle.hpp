@@ -9,6 +9,7 @@
 #include "kernels.hpp"
 #include "kernels2.hpp"
 #include "kernels_batch.hpp"
+#include "fused.hpp"
 
 #include <cstring>
 #include "lb.h"
@@ -35,8 +36,8 @@ struct Layout {
   int v2 = 1;                   // nodes per lane of the stream-collide sweep
   int lb = 10;                  // log2 of the block size of the array layout
   // regions: populations, moments, near-contact flags, reference colours,
-  // reduction scratch
-  size_t f_off = 0, m_off = 0, n_off = 0, c_off = 0, r_off = 0, total = 0;
+  // reduction scratch, progress words of the fused step
+  size_t f_off = 0, m_off = 0, n_off = 0, c_off = 0, r_off = 0, s_off = 0, total = 0;
 };
 
 struct Impl;
@@ -65,6 +66,13 @@ struct lb_handle {
   unsigned char* flag = nullptr;
   lbk::NciParams<float> nq32;
   lbk::NciParams<double> nq64;
+  // fused step: nodes per lane of its kernel (row = 64 fv nodes, 0: the
+  // shape has none), tiling and progress words, the path lb_step takes
+  int fv = 0;
+  int path = 0;         // requested: 0 automatic, 1 two sweeps, 2 fused
+  bool use_fused = false;
+  int order = 0;        // wavefront order of lb_set_sweep_order
+  lbk::FusedParams fp{};
   // per-kernel timing
   std::vector<hipEvent_t> ev;
   int64_t tcap = 0, tcount = 0;
@@ -88,6 +96,10 @@ struct Impl {
   int64_t (*units_sc)(const lb_handle*);
   hipError_t (*batch_moments)(const void* d_desc, int n, int64_t total, hipStream_t s);
   hipError_t (*batch_sc)(const void* d_desc, int n, int64_t total, int v2, hipStream_t s);
+  // fused step for rows of 64 v nodes (nullptr: not built for this
+  // configuration or this v)
+  const void* (*fused_kernel)(int v) = nullptr;
+  hipError_t (*fused)(const lb_handle*) = nullptr;
 };
 
 template <typename C>
@@ -225,12 +237,42 @@ struct ImplT {
     }
     return hipErrorInvalidValue;
   }
+  // Fused step (one species, 3D, FP32 or 16-bit storage): whole rows of
+  // 64 V nodes per wavefront, chunks of up to FE nodes (16-byte accesses).
+  static constexpr bool FUSED = L::D == 3 && sizeof(S) <= 4 && sizeof(C) == 4;
+  static constexpr int FE = sizeof(S) == 2 ? 8 : 4;
+  template <int V>
+  static const void* fused_fn() {
+    constexpr int E = V < FE ? V : FE;
+    return (const void*)&k_fused_step<L, ORDER, S, C, E, V / E, FD>;
+  }
+  static const void* fused_kernel(int v) {
+    if constexpr (FUSED) {
+      switch (v) {
+        case 8: return fused_fn<8>();
+        case 4: return fused_fn<4>();
+        case 2: return fused_fn<2>();
+      }
+    }
+    return nullptr;
+  }
+  static hipError_t fused(const lb_handle* h) {
+    const void* fn = fused_kernel(h->fv);
+    if (!fn) return hipErrorInvalidValue;
+    S* f = (S*)h->f;
+    StepParams<C> p = params_of<C>(h);
+    FusedParams fp = h->fp;
+    void* args[] = {(void*)&f, (void*)&p, (void*)&fp};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)((fp.tiles + 3) / 4)), dim3(256), args, 0,
+                                      h->stream);
+  }
   static const Impl* get() {
     static const Impl impl = {V1,           V2MAX,          EMAX < V2MAX ? EMAX : V2MAX,
                               &moments,     &stream_collide,
                               &init,        &readout,       &conserved,     sizeof(JobDesc<C>),
                               &fill_job_desc<C>, &units_moments, &units_sc, &batch_moments,
-                              &batch_sc};
+                              &batch_sc,    FUSED ? &fused_kernel : nullptr,
+                              FUSED ? &fused : nullptr};
     return &impl;
   }
 };

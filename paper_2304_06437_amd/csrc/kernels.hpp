@@ -112,6 +112,10 @@ __device__ __forceinline__ int64_t node_at(const StepParams<C>& p, int64_t n) {
 template <class L, typename C>
 __device__ __forceinline__ void node_moments(const C (&s)[L::Q], const StepParams<C>& p,
                                              C (&m)[MomentLayout<L>::M]) {
+  // every operation rounded as written: no FMA contraction, whose choices
+  // depend on the surrounding code, so that every kernel evaluating the
+  // moments (and post_collision below) gets the same bits
+#pragma clang fp contract(off)
   using ML = MomentLayout<L>;
   constexpr int D = L::D;
   C drho = s[0];
@@ -205,6 +209,7 @@ template <class L, int ORDER, typename C, bool FD = false>
 __device__ __forceinline__ void post_collision(const C (&m)[MomentLayout<L>::M],
                                                const StepParams<C>& p,
                                                C (&k)[CoefLayout<L, ORDER>::K]) {
+#pragma clang fp contract(off)
   using ML = MomentLayout<L>;
   using CL = CoefLayout<L, ORDER>;
   constexpr int D = L::D;

@@ -185,6 +185,19 @@ int choose_v2(int64_t nx, int vmax) {
   return vmax;
 }
 
+// Nodes per lane of the fused step for this shape, 0 where it has none:
+// one species, 3D, FP32 or 16-bit storage, and rows of exactly 64 v nodes
+// (v = 2, 4, 8 for D3Q19; 2, 4 for D3Q27, whose 512-node rows would not fit
+// one wavefront's registers).
+int fused_rows(const lb_params* p) {
+  if (p->species != 1 || p->lattice == LB_D2Q9) return 0;
+  if (p->storage == LB_STORE_F64 || p->compute != LB_COMPUTE_F32) return 0;
+  const int vmax = p->lattice == LB_D3Q27 ? 4 : 8;
+  for (int v = 2; v <= vmax; v <<= 1)
+    if (p->nx == 64 * (int64_t)v) return v;
+  return 0;
+}
+
 Layout layout_of(const lb_params* p) {
   Layout L;
   L.Q = lattice_q(p->lattice);
@@ -212,7 +225,11 @@ Layout layout_of(const lb_params* p) {
   const bool nci = p->species == 2 && p->nci_strength > 0.0;
   L.c_off = L.n_off + (nci ? align_up((size_t)L.npad, kAlign) : 0);
   L.r_off = L.c_off + (p->species == 2 ? align_up((size_t)L.npad, kAlign) : 0);
-  L.total = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
+  L.s_off = L.r_off + align_up((size_t)kRedBlocks * 8 * sizeof(double), kAlign);
+  // progress words of the fused step: one per tile (at most one per row and
+  // plane) and three more
+  const size_t sync_words = fused_rows(p) ? (size_t)(p->ny * p->nz + 3) : 0;
+  L.total = L.s_off + align_up(sync_words * sizeof(uint32_t), kAlign);
   return L;
 }
 
@@ -276,6 +293,84 @@ int finish_conserved(const lb_handle* h, const double* part, double* out) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// Multiplier of the order permutation u -> (u * mul) mod U of U work units
+// (lb_set_sweep_order): 0 natural, U - 1 reversed, or a multiplier near
+// U/phi that shares no factor with U (mixes distant rows into
+// neighbouring units).
+int64_t order_multiplier(int order, int64_t U) {
+  if (order == 0 || U <= 1) return 0;
+  if (order == 1) return U - 1;
+  int64_t mul = (int64_t)(0.6180339887 * (double)U) | 1;
+  auto gcd = [](int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; };
+  while (mul > 1 && gcd(mul, U) != 1) mul += 2;
+  if (mul >= U) mul = U - 1;
+  return mul;
+}
+
+// Choose the path lb_step takes.  The fused step needs its shape
+// (fused_rows), cooperative launch, and all its tiles resident at once:
+// ny * nzt wavefronts within what the device holds of its kernel.
+// Automatic: at least 8 planes per tile, and the fused step only when its
+// tiles fill at least half of the resident wavefronts.  The progress words
+// are cleared whenever the tiling is set.
+int configure_fused(lb_handle* h, int path, int64_t z_tiles) {
+  if (path == 1) {
+    h->use_fused = false;
+    h->path = 1;
+    return LB_OK;
+  }
+  const void* fn = (h->fv && h->impl->fused_kernel) ? h->impl->fused_kernel(h->fv) : nullptr;
+  const int64_t ny = h->p.ny, nz = h->p.nz;
+  int64_t nzt = 0;
+  bool ok = fn != nullptr;
+  if (ok) {
+    int coop = 0, cus = 0, nb = 0;
+    LB_TRY_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device));
+    LB_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    LB_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0));
+    const int64_t resident = (int64_t)nb * cus * 4;  // wavefronts
+    if (!coop || resident < 1) {
+      ok = false;
+    } else if (z_tiles > 0) {
+      if (z_tiles > nz) return LB_EINVAL;
+      nzt = z_tiles;
+      ok = ny * nzt <= resident;
+    } else {
+      nzt = std::min(std::max<int64_t>(nz / 8, 1), resident / ny);
+      ok = nzt >= 1 && (path == 2 || 2 * ny * nzt >= resident);
+    }
+  }
+  if (!ok) {
+    if (path == 2) return LB_EUNSUPPORTED;
+    h->use_fused = false;
+    h->path = 0;
+    return LB_OK;
+  }
+  h->fp.tiles = ny * nzt;
+  h->fp.nzt = nzt;
+  h->fp.sync = (uint32_t*)((char*)h->base + h->L.s_off);
+  h->fp.stride = (int32_t)((nz + nzt - 1) / nzt + 1);
+  h->fp.order_mul = (int32_t)order_multiplier(h->order, h->fp.tiles);
+  LB_TRY_HIP(hipMemsetAsync(h->fp.sync, 0, (size_t)(h->fp.tiles + 3) * sizeof(uint32_t), h->stream));
+  h->use_fused = true;
+  h->path = path;
+  return LB_OK;
+}
+
+// LB_EDEVICE (once) if a fused step gave up waiting since the last check:
+// its result is invalid.  Called after the stream has drained.
+int fused_status(lb_handle* h) {
+  if (!h->use_fused) return LB_OK;
+  uint32_t* word = h->fp.sync + h->fp.tiles + 2;
+  uint32_t v = 0;
+  LB_TRY_HIP(hipMemcpyAsync(&v, word, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  if (v == 0) return LB_OK;
+  LB_TRY_HIP(hipMemsetAsync(word, 0, sizeof(v), h->stream));
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  return LB_EDEVICE;
+}
+
 extern "C" {
 
 void lb_params_default(lb_params* p) {
@@ -375,6 +470,13 @@ int lb_create(const lb_params* in, void* dev_mem, size_t dev_bytes, void* hip_st
       delete h;
       return status_of(e);
     }
+    h->fv = fused_rows(p);
+    const int fs = configure_fused(h, 0, 0);
+    if (fs != LB_OK) {
+      if (h->owned) (void)hipFree(h->base);
+      delete h;
+      return fs;
+    }
     *out = h;
     return LB_OK;
   } catch (const std::bad_alloc&) {
@@ -431,10 +533,11 @@ int lb_step(lb_handle* h, int64_t nsteps) {
     const bool timed = h->tcount < h->tcap;
     hipEvent_t* ev = timed ? &h->ev[(size_t)4 * h->tcount] : nullptr;
     if (timed) LB_TRY_HIP(hipEventRecord(ev[0], h->stream));
-    LB_TRY_HIP(h->impl->moments(h));
+    if (!h->use_fused) LB_TRY_HIP(h->impl->moments(h));
     if (timed) LB_TRY_HIP(hipEventRecord(ev[1], h->stream));
     if (timed) LB_TRY_HIP(hipEventRecord(ev[2], h->stream));
-    LB_TRY_HIP(h->impl->stream_collide(h));
+    if (h->use_fused) LB_TRY_HIP(h->impl->fused(h));
+    else LB_TRY_HIP(h->impl->stream_collide(h));
     if (timed) {
       LB_TRY_HIP(hipEventRecord(ev[3], h->stream));
       ++h->tcount;
@@ -457,20 +560,38 @@ int lb_sweep(lb_handle* h, int which) {
 int lb_set_sweep_order(lb_handle* h, int order) {
   if (!h || order < 0 || order > 2) return LB_EINVAL;
   const int64_t U = h->p32.nseg * h->p32.ny * h->p32.nz;  // stream-collide wavefronts
-  int64_t mul = 0;
-  if (order == 1) mul = U - 1;
-  if (order == 2) {
-    // a multiplier near U/phi that shares no factor with U (mixes distant
-    // rows into neighbouring units)
-    mul = (int64_t)(0.6180339887 * (double)U) | 1;
-    auto gcd = [](int64_t a, int64_t b) { while (b) { const int64_t t = a % b; a = b; b = t; } return a; };
-    while (mul > 1 && gcd(mul, U) != 1) mul += 2;
-    if (mul >= U) mul = U - 1;
-  }
   if (order != 0 && U >= (int64_t(1) << 31)) return LB_EUNSUPPORTED;
-  if (U <= 1) mul = 0;
+  const int64_t mul = order_multiplier(order, U);
   h->p32.order_mul = (int32_t)mul;
   h->p64.order_mul = (int32_t)mul;
+  h->order = order;
+  if (h->use_fused) h->fp.order_mul = (int32_t)order_multiplier(order, h->fp.tiles);
+  return LB_OK;
+}
+
+int lb_set_step_path(lb_handle* h, int path, int64_t z_tiles) {
+  if (!h || path < 0 || path > 2 || z_tiles < 0) return LB_EINVAL;
+  // drain: the progress words are reset below
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  const int st = fused_status(h);
+  const int prev_path = h->path;
+  const bool prev_use = h->use_fused;
+  const lbk::FusedParams prev = h->fp;
+  const int cs = configure_fused(h, path, path == 1 ? 0 : z_tiles);
+  if (cs != LB_OK) {
+    h->path = prev_path;
+    h->use_fused = prev_use;
+    h->fp = prev;
+    return cs;
+  }
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  return st;
+}
+
+int lb_get_step_path(const lb_handle* h, int* path, int64_t* z_tiles) {
+  if (!h || !path || !z_tiles) return LB_EINVAL;
+  *path = h->use_fused ? 2 : 1;
+  *z_tiles = h->use_fused ? h->fp.nzt : 0;
   return LB_OK;
 }
 
@@ -488,7 +609,8 @@ int lb_layout(const lb_handle* h, size_t* pop_offset, size_t* moment_offset,
 
 int lb_synchronize(lb_handle* h) {
   if (!h) return LB_EINVAL;
-  return launch_status(hipStreamSynchronize(h->stream));
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  return fused_status(h);
 }
 
 int lb_set_stream(lb_handle* h, void* hip_stream) {
@@ -502,6 +624,11 @@ int64_t lb_step_count(const lb_handle* h) { return h ? h->steps : -1; }
 int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
                double* conserved) {
   if (!h) return LB_EINVAL;
+  LB_TRY_HIP(hipStreamSynchronize(h->stream));
+  {
+    const int fst = fused_status(h);
+    if (fst != LB_OK) return fst;
+  }
   const Layout& L = h->L;
   const int64_t N = L.N;
   const bool two = h->p.species == 2;

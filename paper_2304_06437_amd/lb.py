@@ -109,6 +109,9 @@ def load():
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.lb_sweep.argtypes = [H, ctypes.c_int]
     lib.lb_set_sweep_order.argtypes = [H, ctypes.c_int]
+    lib.lb_set_step_path.argtypes = [H, ctypes.c_int, ctypes.c_int64]
+    lib.lb_get_step_path.argtypes = [H, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int64)]
     lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
@@ -199,6 +202,23 @@ def lb_set_sweep_order(h, order: int):
     """0 natural, 1 reversed, 2 strided order of the stream-collide
     sweep's wavefronts (results are bitwise the same)."""
     _check(load().lb_set_sweep_order(h, int(order)), "lb_set_sweep_order")
+
+
+LB_PATH_AUTO, LB_PATH_TWO_SWEEP, LB_PATH_FUSED = 0, 1, 2
+
+
+def lb_set_step_path(h, path: int, z_tiles: int = 0):
+    """Path of lb_step: LB_PATH_AUTO, LB_PATH_TWO_SWEEP or LB_PATH_FUSED
+    (z_tiles runs of planes per row, 0 to choose)."""
+    _check(load().lb_set_step_path(h, int(path), int(z_tiles)), "lb_set_step_path")
+
+
+def lb_get_step_path(h):
+    """(path lb_step takes: LB_PATH_TWO_SWEEP or LB_PATH_FUSED, z_tiles)."""
+    path = ctypes.c_int(0)
+    zt = ctypes.c_int64(0)
+    _check(load().lb_get_step_path(h, ctypes.byref(path), ctypes.byref(zt)), "lb_get_step_path")
+    return path.value, zt.value
 
 
 def lb_layout(h):

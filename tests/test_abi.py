@@ -93,8 +93,11 @@ def test_required_bytes_match_paper_array_counts():
         N = 256 * 256 * nz
         arrays = g[name][0]
         extra = lb.lb_required_bytes(p) - arrays * 4 * N
-        # only the FP64 reduction scratch (64 KiB) and alignment remain
-        assert 0 <= extra <= 64 * 1024 + 256 * (arrays + 2), (name, extra)
+        # only the FP64 reduction scratch (64 KiB), the fused step's progress
+        # words (one per row and plane, 3D rows of 256 nodes) and alignment
+        # remain
+        words = 4 * (256 * nz + 3) if nz > 1 else 0
+        assert 0 <= extra - words <= 64 * 1024 + 256 * (arrays + 3), (name, extra)
         # saving against the flip-flop layout, bytes per node (Section 4)
         assert (g[name][1] - arrays) * 4 == g[name][2]
 
@@ -106,8 +109,9 @@ def test_required_bytes_scale_with_precision():
     b64 = lb.lb_required_bytes(lb.lb_params_default(storage=lb.LB_STORE_F64,
                                                     compute=lb.LB_COMPUTE_F64, **base))
     N = 128 ** 3
+    words = 4 * (128 * 128 + 3)  # the fused step's progress words: FP32 and 16-bit only
     assert abs((b32 - b16) - 19 * 2 * N) < 4096
-    assert abs((b64 - b32) - 29 * 4 * N) < 4096
+    assert abs((b64 - (b32 - words)) - 29 * 4 * N) < 4096
 
 
 def test_strerror_and_null_destroy():
@@ -120,20 +124,33 @@ def test_strerror_and_null_destroy():
     assert lb.load().lb_set_stream(None, None) == lb.LB_EINVAL
 
 
-def _blocked_bytes(Q, M, NS, ssize, csize, species=1):
+def _fused_rows(kw):
+    """The fused step's shapes (lb_set_step_path): one species, D3Q19 or
+    D3Q27, FP32 or 16-bit storage, nx = 128, 256, 512 (D3Q27: 128, 256)."""
+    if kw.get("species", 1) != 1 or kw.get("lattice", 19) == 9:
+        return False
+    if kw.get("storage", lb.LB_STORE_F32) == lb.LB_STORE_F64:
+        return False
+    sizes = (128, 256) if kw.get("lattice", 19) == 27 else (128, 256, 512)
+    return kw.get("nx", 32) in sizes
+
+
+def _blocked_bytes(Q, M, NS, ssize, csize, species=1, rows=0):
     """Footprint of the documented blocked layout over NS storage nodes:
     block B = 32 KiB of population storage (at least 1024 nodes, at most the
     next power of two >= NS), node count padded to a multiple of B, each
     region 256-byte aligned, plus (two species) one reference-colour byte per
-    padded node, plus 64 KiB of FP64 reduction partials."""
+    padded node, plus 64 KiB of FP64 reduction partials, plus (shapes of the
+    fused step) a 4-byte progress word per row (rows = ny nz) and 3 more."""
     B = 1024
     while B < NS and B * ssize < 32768:
         B *= 2
     npad = -(-NS // B) * B
     al = lambda v: -(-v // 256) * 256
     ref = al(npad) if species == 2 else 0
-    return (al(species * Q * npad * ssize) + al(M * npad * csize) + ref + al(1024 * 8 * 8), B,
-            npad)
+    sync = al(4 * (rows + 3)) if rows else 0
+    return (al(species * Q * npad * ssize) + al(M * npad * csize) + ref + al(1024 * 8 * 8) + sync,
+            B, npad)
 
 
 def test_required_bytes_of_ragged_domains():
@@ -164,10 +181,18 @@ def test_required_bytes_of_ragged_domains():
               compute=lb.LB_COMPUTE_F64), 19, 11, 8, 8, 2, 132),
         (dict(lattice=19, nx=511, ny=3, nz=2), 19, 10, 4, 4, 1, 512),     # V = 4
         (dict(lattice=19, nx=64, ny=3, nz=2, storage=f16), 19, 10, 2, 4, 1, 64),   # V = 1
+        # shapes of the fused step: progress words
+        (dict(lattice=19, nx=128, ny=7, nz=5), 19, 10, 4, 4, 1, 128),
+        (dict(lattice=19, nx=512, ny=3, nz=9, storage=f16), 19, 10, 2, 4, 1, 512),
+        (dict(lattice=27, nx=256, ny=4, nz=6, hermite_order=3), 27, 10, 4, 4, 1, 256),
+        (dict(lattice=27, nx=512, ny=4, nz=6), 27, 10, 4, 4, 1, 512),
+        (dict(lattice=19, nx=256, ny=5, nz=3, storage=f64, compute=lb.LB_COMPUTE_F64), 19, 10,
+         8, 8, 1, 256),
     ]
     for kw, Q, M, ss, cs, sp, px in cases:
         p = lb.lb_params_default(**kw)
-        want, B, npad = _blocked_bytes(Q, M, px * p.ny * p.nz, ss, cs, sp)
+        rows = p.ny * p.nz if _fused_rows(kw) else 0
+        want, B, npad = _blocked_bytes(Q, M, px * p.ny * p.nz, ss, cs, sp, rows)
         assert lb.lb_required_bytes(p) == want, (kw, px, B, npad)
 
 

@@ -1,0 +1,191 @@
+"""The fused step (lb_set_step_path) against the two-sweep step and the oracle.
+
+The fused step computes every node's moments and post-collision populations
+with the two sweeps' arithmetic, keeping the moments in registers; its
+population memory after any number of steps must equal the two-sweep
+step's byte for byte.  Cases cover the tilings (one run of planes per row,
+uneven runs, one plane per run), every boundary kind the tiles meet
+(periodic wrap in y and z, bounce-back walls on each axis, moving walls),
+the body force, 16-bit storage, D3Q27 second and third order (the latter
+with 16-bit storage takes the short division), degenerate rows and planes
+(ny = 1, ny = 2, nz = 1), and permuted tile orders.  The FP32 fused step is
+also held to the oracle directly at the FP32 bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2304_06437_amd import inputs, lb
+from paper_2304_06437_amd.sim import Simulation, make_params, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _lid(axis, side, comp, v):
+    w = np.zeros((3, 2, 3))
+    w[axis][side][comp] = v
+    return w
+
+
+# name: (make_params keywords, z_tiles for the fused step, steps)
+CASES = {
+    "d3q19_periodic_one_run": (dict(lattice=19, shape=(128, 12, 20)), 1, 7),
+    "d3q19_periodic_uneven_runs": (dict(lattice=19, shape=(128, 12, 20)), 3, 7),
+    "d3q19_periodic_one_plane_runs": (dict(lattice=19, shape=(128, 6, 8)), 8, 5),
+    "d3q19_walls_yz_force": (dict(lattice=19, shape=(128, 10, 16), bc=(0, 1, 1),
+                                  force=(1e-5, 0.0, 2e-6)), 4, 9),
+    "d3q19_walls_x": (dict(lattice=19, shape=(128, 8, 8), bc=(1, 0, 0)), 2, 6),
+    "d3q19_walls_xyz_moving": (dict(lattice=19, shape=(128, 16, 12), bc=(1, 1, 1),
+                                    wall_velocity=_lid(1, 1, 0, 0.05) + _lid(2, 0, 1, -0.03)),
+                               3, 8),
+    "d3q19_ny1": (dict(lattice=19, shape=(128, 1, 16)), 4, 6),
+    "d3q19_ny2": (dict(lattice=19, shape=(128, 2, 16)), 2, 6),
+    "d3q19_nz1": (dict(lattice=19, shape=(128, 8, 1)), 1, 6),
+    "d3q19_nz1_wall": (dict(lattice=19, shape=(128, 8, 1), bc=(0, 0, 1)), 1, 6),
+    "d3q19_256_f32": (dict(lattice=19, shape=(256, 9, 10), tau=0.55), 2, 6),
+    "d3q19_512_f32": (dict(lattice=19, shape=(512, 6, 10), tau=0.55), 3, 6),
+    "d3q19_256_f16s": (dict(lattice=19, shape=(256, 6, 10), storage="f16s"), 2, 6),
+    "d3q19_512_bf16s_walls": (dict(lattice=19, shape=(512, 4, 6), storage="bf16s", bc=(0, 1, 0)),
+                              2, 6),
+    "d3q19_128_f16s_walls_z": (dict(lattice=19, shape=(128, 6, 9), storage="f16s", bc=(0, 0, 1)),
+                               3, 6),
+    "d3q27_o2_128": (dict(lattice=27, shape=(128, 6, 8)), 2, 5),
+    "d3q27_o3_256_walls": (dict(lattice=27, shape=(256, 5, 6), order=3, bc=(0, 1, 1)), 2, 5),
+    "d3q27_o3_128_f16s": (dict(lattice=27, shape=(128, 6, 6), order=3, storage="f16s"), 3, 5),
+}
+
+
+def _fields(p, seed):
+    N = p.nx * p.ny * p.nz
+    return inputs.random_state(N, 3, seed=seed, drho=1e-2, du=0.04)
+
+
+def _pop_bytes(sim):
+    pop_off, _, B, npad, _ = lb.lb_layout(sim.handle)
+    Q = {lb.LB_D3Q19: 19, lb.LB_D3Q27: 27}[sim.params.lattice]
+    ss = {lb.LB_STORE_F32: 4, lb.LB_STORE_F16S: 2, lb.LB_STORE_BF16S: 2}[sim.params.storage]
+    return sim.buffer[pop_off:pop_off + Q * npad * ss]
+
+
+def _pair(kw, z_tiles, steps, seed, order=0):
+    p = make_params(**kw)
+    rho, u = _fields(p, seed)
+    sims = []
+    for path in (lb.LB_PATH_TWO_SWEEP, lb.LB_PATH_FUSED):
+        sim = Simulation(p)
+        lb.lb_set_step_path(sim.handle, path, z_tiles)
+        if order:
+            lb.lb_set_sweep_order(sim.handle, order)
+        sim.init(rho, u)
+        sims.append(sim)
+    assert lb.lb_get_step_path(sims[0].handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+    assert lb.lb_get_step_path(sims[1].handle) == (lb.LB_PATH_FUSED, z_tiles)
+    for sim in sims:
+        sim.step(steps)
+        sim.synchronize()
+    return sims
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fused_equals_two_sweeps_bitwise(case):
+    kw, z_tiles, steps = CASES[case]
+    a, b = _pair(kw, z_tiles, steps, seed=len(case))
+    ra, rb = _pop_bytes(a), _pop_bytes(b)
+    diff = int((ra != rb).sum().item())
+    print(f"{case}: {steps} steps, {z_tiles} runs per row, {diff} differing bytes of {ra.numel()}")
+    assert diff == 0
+    ma = a.moments(conserved=True)
+    mb = b.moments(conserved=True)
+    for key in ("rho", "u", "pineq", "conserved"):
+        assert np.array_equal(ma[key], mb[key]), key
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_fused_tile_order_does_not_matter(order):
+    """Tiles handed to wavefronts in reversed or strided order (so that
+    neighbouring rows run on distant workgroups and dies)."""
+    kw = dict(lattice=19, shape=(256, 24, 16), bc=(0, 1, 0), force=(1e-5, 0, 0))
+    a, b = _pair(kw, 4, 6, seed=11, order=order)
+    assert torch.equal(_pop_bytes(a), _pop_bytes(b))
+    a.close()
+    b.close()
+
+
+def test_fused_fp32_against_oracle():
+    """Channel with walls in z and a body force along x, 300 steps: the FP32
+    fused step within the FP32 bar of the FP64 oracle."""
+    nx, ny, nz, steps = 128, 6, 16, 300
+    kw = dict(tau=0.6, force=(2e-6, 0.0, 0.0))
+    p = make_params(lattice=19, shape=(nx, ny, nz), bc=(0, 0, 1), **kw)
+    rho, u = _fields(p, 5)
+    with Simulation(p) as sim:
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 2)
+        sim.init(rho, u)
+        sim.step(steps)
+        got = sim.moments(pineq=False, conserved=False)
+    q = oracle.Params(lattice=19, nx=nx, ny=ny, nz=nz, bb=(0, 0, 1), **kw)
+    ref = oracle.simulate(q, rho, u, steps)
+    err = max_rel(got["u"], ref["u"])
+    print(f"fused FP32 channel, {steps} steps: max-rel u {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_path_selection_and_limits():
+    # automatic: a domain whose tiles fill the device takes the fused step
+    big = make_params(lattice=19, shape=(512, 512, 16))
+    with Simulation(big) as sim:
+        path, zt = lb.lb_get_step_path(sim.handle)
+        print("512 x 512 x 16:", path, zt)
+        assert path == lb.LB_PATH_FUSED and zt >= 1
+    # a small one keeps the two sweeps unless asked
+    small = make_params(lattice=19, shape=(128, 8, 8))
+    with Simulation(small) as sim:
+        assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 0)
+        assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED
+        with pytest.raises(lb.LbError) as e:
+            lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 9)  # more runs than planes
+        assert e.value.status == lb.LB_EINVAL
+        assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED  # unchanged
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_TWO_SWEEP, 0)
+        assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+    # shapes without a fused step
+    for kw in (dict(lattice=9, shape=(128, 64, 1)), dict(lattice=19, shape=(100, 8, 8)),
+               dict(lattice=19, shape=(128, 8, 8), storage="f64"),
+               dict(lattice=27, shape=(512, 4, 4)),
+               dict(lattice=19, shape=(128, 8, 8), species=2, sigma=0.03, beta=0.7)):
+        with Simulation(make_params(**kw)) as sim:
+            assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+            with pytest.raises(lb.LbError) as e:
+                lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 0)
+            assert e.value.status == lb.LB_EUNSUPPORTED
+    # more rows than resident wavefronts
+    tall = make_params(lattice=19, shape=(128, 40000, 2))
+    with Simulation(tall) as sim:
+        with pytest.raises(lb.LbError) as e:
+            lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 1)
+        assert e.value.status == lb.LB_EUNSUPPORTED
+
+
+def test_fused_full_size_equals_two_sweeps():
+    """The benchmark's shape, D3Q19 512^3 FP32 periodic Taylor-Green, 3 steps
+    through the automatic path (fused) and the two sweeps: equal bytes."""
+    n = 512
+    p = make_params(lattice=19, shape=(n, n, n), tau=0.55)
+    rho, u = inputs.taylor_green_3d(n, n, n, 0.02)
+    sims = []
+    for path in (lb.LB_PATH_AUTO, lb.LB_PATH_TWO_SWEEP):
+        sim = Simulation(p)
+        lb.lb_set_step_path(sim.handle, path, 0)
+        sim.init(rho, u)
+        sims.append(sim)
+    assert lb.lb_get_step_path(sims[0].handle)[0] == lb.LB_PATH_FUSED
+    for sim in sims:
+        sim.step(3)
+        sim.synchronize()
+    assert torch.equal(_pop_bytes(sims[0]), _pop_bytes(sims[1]))
+    for sim in sims:
+        sim.close()
