@@ -378,6 +378,16 @@ int lb_timing_begin(lb_handle* h, int64_t max_steps);
  * report its kernel at index 1 and no time at index 0. */
 int lb_timing_end(lb_handle* h, double* ms, int64_t* launches);
 
+/* Self-check of the short division of the post-collision coefficients
+ * (x r plus one correction with the exact FMA residual, used by the
+ * instruction-bound kernels in place of the IEEE division): for each odd
+ * divisor d = 3, 9, 27 that the lattices need, the number of finite FP32
+ * inputs x (all 2^32 bit patterns) whose quotient x / d differs in any bit
+ * from the IEEE quotient; 0 means the two divisions are interchangeable.
+ * Runs on hip_stream and waits for it; a few tenths of a second.
+ * mismatches[3].  LB_EINVAL for NULL. */
+int lb_check_division(void* hip_stream, uint64_t* mismatches);
+
 /* Plain device-to-device copy kernel (bytes a multiple of 16, both pointers
  * 16-byte aligned), enqueued on hip_stream: the practical bandwidth ceiling
  * for the sweeps and the scale for hardware byte counters. */

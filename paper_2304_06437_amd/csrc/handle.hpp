@@ -244,7 +244,9 @@ struct ImplT {
   template <int V>
   static const void* fused_fn() {
     constexpr int E = V < FE ? V : FE;
-    return (const void*)&k_fused_step<L, ORDER, S, C, E, V / E, FD>;
+    // the short division (same bits as the IEEE one in FP32, see scaled):
+    // the fused step is bound by its arithmetic, not by bandwidth
+    return (const void*)&k_fused_step<L, ORDER, S, C, E, V / E, true>;
   }
   static const void* fused_kernel(int v) {
     if constexpr (FUSED) {

@@ -164,10 +164,14 @@ __device__ __forceinline__ void node_moments(const C (&s)[L::Q], const StepParam
 // same relative error with the same sign at every node and step, which
 // accumulates as a drift of the conserved momentum.)  Two ways to divide:
 //   FD = false: IEEE division, correctly rounded;
-//   FD = true:  q = x r, then one Newton correction with the exact FMA
-//               residual, q' = q + (x - q d) r: within an ulp of x / d, no
-//               fixed sign, three instructions instead of about ten.
-// The stream-collide sweeps bound by instruction issue (D3Q27 third order
+//   FD = true:  q = x r, then one correction with the exact FMA residual,
+//               q' = q + (x - q d) r (Markstein's correction), with the sign
+//               of x (it rounds -0 / d to +0 otherwise): four instructions
+//               instead of about ten.  In FP32, for the odd divisors d = 3,
+//               9, 27 that occur here, q' equals the IEEE quotient for every
+//               finite input (checked exhaustively by lb_check_division), so
+//               the choice changes speed, never a result bit.
+// The sweeps bound by instruction issue (the fused step, D3Q27 third order
 // with 16-bit storage) use FD = true; the bandwidth-bound ones measure
 // faster with the IEEE sequence.
 __host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
@@ -186,13 +190,31 @@ __device__ __forceinline__ C scaled(C x) {
       constexpr C r = C(1) / C(dodd);
       const C q = y * r;
       const C e = fma(-q, C(dodd), y);  // exact: q is within an ulp of y / d
-      y = fma(e, r, q);
+      y = copysign(fma(e, r, q), y);
     } else {
       y = y / C(dodd);
     }
   }
   if constexpr (d2 != 1) y = y * C(1.0 / d2);
   return y;
+}
+
+// Exhaustive check of the short division against the IEEE one: every
+// finite FP32 input x (bit pattern i in [0, 2^32)), x / D both ways, counted
+// where the bits differ.  Grid-stride; one counter per launch.
+template <int D>
+__global__ __launch_bounds__(256) void k_division_check(unsigned long long* mismatches) {
+  const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+  unsigned long long bad = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t(1) << 32);
+       i += nthr) {
+    const float x = __uint_as_float((uint32_t)i);
+    if (!isfinite(x)) continue;
+    const float a = scaled<1, D, true, float>(x);
+    const float b = scaled<1, D, false, float>(x);
+    if (__float_as_uint(a) != __float_as_uint(b)) ++bad;
+  }
+  if (bad) atomicAdd(mismatches, bad);
 }
 
 // Post-collision Hermite coefficients of a node from its moments.  With

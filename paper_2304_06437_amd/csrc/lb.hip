@@ -743,6 +743,27 @@ int lb_timing_end(lb_handle* h, double* ms, int64_t* launches) {
   return LB_OK;
 }
 
+int lb_check_division(void* hip_stream, uint64_t* mismatches) {
+  if (!mismatches) return LB_EINVAL;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  unsigned long long* d = nullptr;
+  LB_TRY_HIP(hipMalloc(&d, 3 * sizeof(unsigned long long)));
+  unsigned long long h[3] = {0, 0, 0};
+  hipError_t e = hipMemsetAsync(d, 0, sizeof(h), st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_division_check<3>, dim3(16384), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_division_check<9>, dim3(16384), dim3(256), 0, st, d + 1);
+    hipLaunchKernelGGL(k_division_check<27>, dim3(16384), dim3(256), 0, st, d + 2);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return status_of(e);
+  for (int i = 0; i < 3; ++i) mismatches[i] = h[i];
+  return LB_OK;
+}
+
 int lb_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   if (!dst || !src || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
     return LB_EINVAL;

@@ -107,6 +107,7 @@ def load():
     lib.lb_timing_begin.argtypes = [H, ctypes.c_int64]
     lib.lb_timing_end.argtypes = [H, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.lb_check_division.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
     lib.lb_sweep.argtypes = [H, ctypes.c_int]
     lib.lb_set_sweep_order.argtypes = [H, ctypes.c_int]
     lib.lb_set_step_path.argtypes = [H, ctypes.c_int, ctypes.c_int64]
@@ -219,6 +220,14 @@ def lb_get_step_path(h):
     zt = ctypes.c_int64(0)
     _check(load().lb_get_step_path(h, ctypes.byref(path), ctypes.byref(zt)), "lb_get_step_path")
     return path.value, zt.value
+
+
+def lb_check_division(stream=None):
+    """Mismatches of the short division against the IEEE one over every
+    finite FP32 input, for the divisors (3, 9, 27)."""
+    out = (ctypes.c_uint64 * 3)()
+    _check(load().lb_check_division(stream, out), "lb_check_division")
+    return tuple(int(v) for v in out)
 
 
 def lb_layout(h):
