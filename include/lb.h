@@ -216,8 +216,10 @@ int lb_set_sweep_order(lb_handle* h, int order);
  *   FP32 arithmetic, nx = 128, 256 or 512 (D3Q27: 128, 256); every tile
  *   must be resident at once (ny * z_tiles wavefronts), and the device
  *   must support cooperative launch.
- *   path: LB_PATH_AUTO (what lb_create sets: fused where the shape allows
- *   it and its tiles fill at least half the device, else two sweeps),
+ *   path: LB_PATH_AUTO (what lb_create sets: fused for D3Q19 where the
+ *   shape allows it and its tiles fill at least half the device, else two
+ *   sweeps; D3Q27 takes the fused step only when asked, its two sweeps
+ *   being faster),
  *   LB_PATH_TWO_SWEEP, LB_PATH_FUSED.  z_tiles: runs of planes per row,
  *   0 to choose (at least 8 planes per run); ignored for two sweeps.
  * Waits for the handle's stream.  LB_EUNSUPPORTED if LB_PATH_FUSED cannot

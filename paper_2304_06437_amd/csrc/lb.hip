@@ -310,9 +310,11 @@ int64_t order_multiplier(int order, int64_t U) {
 // Choose the path lb_step takes.  The fused step needs its shape
 // (fused_rows), cooperative launch, and all its tiles resident at once:
 // ny * nzt wavefronts within what the device holds of its kernel.
-// Automatic: at least 8 planes per tile, and the fused step only when its
-// tiles fill at least half of the resident wavefronts.  The progress words
-// are cleared whenever the tiling is set.
+// Automatic: D3Q19 only (the D3Q27 fused kernels, one wavefront per SIMD
+// with their larger arithmetic, measure slower than the two sweeps), at
+// least 8 planes per tile, and the fused step only when its tiles fill at
+// least half of the resident wavefronts.  The progress words are cleared
+// whenever the tiling is set.
 int configure_fused(lb_handle* h, int path, int64_t z_tiles) {
   if (path == 1) {
     h->use_fused = false;
@@ -320,6 +322,7 @@ int configure_fused(lb_handle* h, int path, int64_t z_tiles) {
     return LB_OK;
   }
   const void* fn = (h->fv && h->impl->fused_kernel) ? h->impl->fused_kernel(h->fv) : nullptr;
+  if (path == 0 && h->p.lattice != LB_D3Q19) fn = nullptr;
   const int64_t ny = h->p.ny, nz = h->p.nz;
   int64_t nzt = 0;
   bool ok = fn != nullptr;

@@ -152,6 +152,11 @@ def test_path_selection_and_limits():
         assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED  # unchanged
         lb.lb_set_step_path(sim.handle, lb.LB_PATH_TWO_SWEEP, 0)
         assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+    # D3Q27 keeps the two sweeps unless asked (its fused kernels are slower)
+    with Simulation(make_params(lattice=27, shape=(256, 256, 64))) as sim:
+        assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_TWO_SWEEP, 0)
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 0)
+        assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED
     # shapes without a fused step
     for kw in (dict(lattice=9, shape=(128, 64, 1)), dict(lattice=19, shape=(100, 8, 8)),
                dict(lattice=19, shape=(128, 8, 8), storage="f64"),
