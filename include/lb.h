@@ -236,6 +236,13 @@ int lb_set_step_path(lb_handle* h, int path, int64_t z_tiles);
  * fused step, its runs of planes per row (0 for two sweeps). */
 int lb_get_step_path(const lb_handle* h, int* path, int64_t* z_tiles);
 
+/* Bound of every wait of the fused step, in polls of a neighbouring row's
+ * progress word (default 2^22, seconds at worst); a wait that exhausts it
+ * gives up (see lb_set_step_path).  For tests of that path: 0 makes every
+ * wait that is not met at its first poll give up.  Applies to later steps.
+ * LB_EINVAL for a negative bound or one above INT32_MAX. */
+int lb_set_fused_wait_limit(lb_handle* h, int64_t polls);
+
 /* Device layout of the handle's state, for tests and tools.  The population
  * region (species*Q arrays of the storage type: set 0 then set 1) starts at
  * byte pop_offset of the device buffer, the moment region (M arrays of the

@@ -41,7 +41,7 @@
 // Progress.  Waits need every tile running at once: the host sizes the
 // tiles so that all of them are resident and launches cooperatively (the
 // launch fails instead of queueing tiles).  Every wait is bounded: past
-// kFusedSpinLimit polls it raises the abort word and stops waiting (the
+// kFusedWaitLimit polls it raises the abort word and stops waiting (the
 // step's result is then invalid and the host reports an error), so every
 // wavefront ends.  The progress words count in epochs: a step reads the
 // epoch at its start, counts from epoch x stride, and the last wavefront
@@ -54,14 +54,16 @@
 namespace lbk {
 
 struct FusedParams {
-  int64_t tiles;      // ny * nzt
-  int64_t nzt;        // tiles along z
-  uint32_t* sync;     // progress[tiles], then done counter, epoch, abort
-  int32_t stride;     // progress units per step (longest tile + 1)
-  int32_t order_mul;  // tile order permutation (0 = natural), as StepParams::order_mul
+  int64_t tiles;       // ny * nzt
+  int64_t nzt;         // tiles along z
+  uint32_t* sync;      // progress[tiles], then done counter, epoch, abort
+  int32_t stride;      // progress units per step (longest tile + 1)
+  int32_t order_mul;   // tile order permutation (0 = natural), as StepParams::order_mul
+  int32_t wait_limit;  // polls before a wait gives up (kFusedWaitLimit)
+  int32_t pad_;
 };
 
-constexpr int kFusedSpinLimit = 1 << 22;
+constexpr int32_t kFusedWaitLimit = 1 << 22;
 
 __device__ __forceinline__ uint32_t sync_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -109,16 +111,20 @@ struct FusedSweep {
     if (tl.lane == 0) sync_store(fp.sync + tl.t, tl.base + planes);
     asm volatile("" ::: "memory");
   }
-  // until tile u has read `planes` planes of this step (or the abort word is up)
+  // until tile u has read `planes` planes of this step, or the abort word is
+  // up, or wait_limit polls have failed (then it raises the abort word)
   __device__ __forceinline__ static void wait_for(const FusedParams& fp, const Tile& tl, int64_t u,
                                   uint32_t planes) {
     const uint32_t need = tl.base + planes;
     uint32_t* abort_word = fp.sync + fp.tiles + 2;
-    for (int it = 0; it < kFusedSpinLimit; ++it) {
+    for (int32_t it = 0;; ++it) {
       if ((int32_t)(sync_load(fp.sync + u) - need) >= 0) break;
       if (sync_load(abort_word) != 0) break;
+      if (it >= fp.wait_limit) {
+        if (tl.lane == 0) sync_store(abort_word, 1u);
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
-      if (it == kFusedSpinLimit - 1) sync_store(abort_word, 1u);
     }
     asm volatile("" ::: "memory");
   }

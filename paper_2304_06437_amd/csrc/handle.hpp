@@ -72,6 +72,7 @@ struct lb_handle {
   int path = 0;         // requested: 0 automatic, 1 two sweeps, 2 fused
   bool use_fused = false;
   int order = 0;        // wavefront order of lb_set_sweep_order
+  int32_t wait_limit = lbk::kFusedWaitLimit;  // lb_set_fused_wait_limit
   lbk::FusedParams fp{};
   // per-kernel timing
   std::vector<hipEvent_t> ev;

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -354,6 +355,7 @@ int configure_fused(lb_handle* h, int path, int64_t z_tiles) {
   h->fp.sync = (uint32_t*)((char*)h->base + h->L.s_off);
   h->fp.stride = (int32_t)((nz + nzt - 1) / nzt + 1);
   h->fp.order_mul = (int32_t)order_multiplier(h->order, h->fp.tiles);
+  h->fp.wait_limit = h->wait_limit;
   LB_TRY_HIP(hipMemsetAsync(h->fp.sync, 0, (size_t)(h->fp.tiles + 3) * sizeof(uint32_t), h->stream));
   h->use_fused = true;
   h->path = path;
@@ -589,6 +591,13 @@ int lb_set_step_path(lb_handle* h, int path, int64_t z_tiles) {
   }
   LB_TRY_HIP(hipStreamSynchronize(h->stream));
   return st;
+}
+
+int lb_set_fused_wait_limit(lb_handle* h, int64_t polls) {
+  if (!h || polls < 0 || polls > INT32_MAX) return LB_EINVAL;
+  h->wait_limit = (int32_t)polls;
+  h->fp.wait_limit = h->wait_limit;
+  return LB_OK;
 }
 
 int lb_get_step_path(const lb_handle* h, int* path, int64_t* z_tiles) {

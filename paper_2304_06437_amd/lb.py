@@ -113,6 +113,7 @@ def load():
     lib.lb_set_step_path.argtypes = [H, ctypes.c_int, ctypes.c_int64]
     lib.lb_get_step_path.argtypes = [H, ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.lb_set_fused_wait_limit.argtypes = [H, ctypes.c_int64]
     lib.lb_layout.argtypes = [H, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                               ctypes.POINTER(ctypes.c_int64)]
@@ -212,6 +213,11 @@ def lb_set_step_path(h, path: int, z_tiles: int = 0):
     """Path of lb_step: LB_PATH_AUTO, LB_PATH_TWO_SWEEP or LB_PATH_FUSED
     (z_tiles runs of planes per row, 0 to choose)."""
     _check(load().lb_set_step_path(h, int(path), int(z_tiles)), "lb_set_step_path")
+
+
+def lb_set_fused_wait_limit(h, polls: int):
+    """Polls before a wait of the fused step gives up (tests of that path)."""
+    _check(load().lb_set_fused_wait_limit(h, int(polls)), "lb_set_fused_wait_limit")
 
 
 def lb_get_step_path(h):

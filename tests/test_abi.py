@@ -122,6 +122,9 @@ def test_strerror_and_null_destroy():
     assert lb.load().lb_moments(None, None, None, None, None, None) == lb.LB_EINVAL
     assert lb.load().lb_copy(None, None, 16, None) == lb.LB_EINVAL
     assert lb.load().lb_set_stream(None, None) == lb.LB_EINVAL
+    assert lb.load().lb_set_step_path(None, 0, 0) == lb.LB_EINVAL
+    assert lb.load().lb_set_fused_wait_limit(None, 1) == lb.LB_EINVAL
+    assert lb.load().lb_check_division(None, None) == lb.LB_EINVAL
 
 
 def _fused_rows(kw):

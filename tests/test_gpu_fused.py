@@ -194,3 +194,37 @@ def test_fused_full_size_equals_two_sweeps():
     assert torch.equal(_pop_bytes(sims[0]), _pop_bytes(sims[1]))
     for sim in sims:
         sim.close()
+
+
+def test_fused_wait_bound_gives_up_and_recovers():
+    """With a bound of 0 polls, any wait that is not met at its first poll
+    gives up: every wavefront still ends, the steps' result is invalid, and
+    the next synchronize reports LB_EDEVICE once.  With the default bound
+    back, the same handle steps byte for byte like the two sweeps."""
+    p = make_params(lattice=19, shape=(256, 64, 64))
+    rho, u = _fields(p, 3)
+    with Simulation(p) as sim:
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_FUSED, 4)
+        lb.lb_set_fused_wait_limit(sim.handle, 0)
+        sim.init(rho, u)
+        sim.step(20)
+        st = lb.load().lb_synchronize(sim.handle)
+        print("status after 20 steps with a bound of 0 polls:", st)
+        assert st == lb.LB_EDEVICE
+        assert lb.load().lb_synchronize(sim.handle) == lb.LB_OK  # reported once
+        lb.lb_set_fused_wait_limit(sim.handle, 1 << 22)
+        sim.init(rho, u)
+        sim.step(6)
+        sim.synchronize()
+        fused = _pop_bytes(sim).clone()
+    with Simulation(p) as ref:
+        lb.lb_set_step_path(ref.handle, lb.LB_PATH_TWO_SWEEP, 0)
+        ref.init(rho, u)
+        ref.step(6)
+        ref.synchronize()
+        assert torch.equal(fused, _pop_bytes(ref))
+    with Simulation(p) as sim:
+        for bad in (-1, 1 << 31):
+            with pytest.raises(lb.LbError) as e:
+                lb.lb_set_fused_wait_limit(sim.handle, bad)
+            assert e.value.status == lb.LB_EINVAL
