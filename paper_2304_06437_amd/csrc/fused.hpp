@@ -130,6 +130,11 @@ struct FusedSweep {
   }
 
   // -- one plane of the row --------------------------------------------------
+  // Storage node of the row's first node.  A row never straddles a block of
+  // the array layout (the row pitch, 64 E H = nx, divides the block size,
+  // both powers of two; the host checks it), so element (a, row start + x)
+  // is at slot(row start) + a B + x: a wave-uniform base plus the lane's
+  // offset, with no per-lane 64-bit index arithmetic.
   __device__ __forceinline__ static int64_t row_of(const StepParams<C>& p, int64_t y, int64_t z) {
     return p.px * (y + p.ny * z);
   }
@@ -140,7 +145,7 @@ struct FusedSweep {
     for (int a = 0; a < Q; ++a)
 #pragma unroll
       for (int h = 0; h < H; ++h)
-        load_pack<S, C, E>(f + slot<Q>(p, rowbase + h * 64 * E + lane * E) + a * astride(p),
+        load_pack<S, C, E>(f + slot<Q>(p, rowbase) + a * astride(p) + (h * 64 * E + lane * E),
                            raw[a][h]);
   }
 
@@ -211,7 +216,7 @@ struct FusedSweep {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const int64_t xs = (int64_t)h * 64 * E + lane * E;
-      S* dst = f + slot<Q>(p, trow + xs) + A * astride(p);
+      S* dst = f + slot<Q>(p, trow) + A * astride(p) + xs;
       const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);
       const bool cut_hi = (cx < 0) && p.bbx && (xs + E == p.nx);
       if (!(cut_lo || cut_hi)) {
@@ -238,7 +243,7 @@ struct FusedSweep {
       if (lane == 63) {
         const C v = p.moving ? link_value_plus<L, ORDER, A, C>(k[H - 1][E - 1], wall_dot<L, A, C>(p, 1))
                              : link_value<L, ORDER, A, C>(k[H - 1][E - 1]);
-        f[slot<Q>(p, rowbase + p.nx - 1) + AB * astride(p)] = Codec<S, C>::store(v);
+        f[slot<Q>(p, rowbase) + AB * astride(p) + (p.nx - 1)] = Codec<S, C>::store(v);
       }
     } else if constexpr (cx < 0) {
       if (lane == 0) {
@@ -279,7 +284,7 @@ struct FusedSweep {
           bv[e] = link_value_plus<L, ORDER, A, C>(k[h][e], extra);
         }
       }
-      store_pack<S, C, E>(f + slot<Q>(p, rowbase + xs) + AB * astride(p), bv);
+      store_pack<S, C, E>(f + slot<Q>(p, rowbase) + AB * astride(p) + xs, bv);
     }
   }
 

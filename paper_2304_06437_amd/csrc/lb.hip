@@ -324,6 +324,9 @@ int configure_fused(lb_handle* h, int path, int64_t z_tiles) {
   }
   const void* fn = (h->fv && h->impl->fused_kernel) ? h->impl->fused_kernel(h->fv) : nullptr;
   if (path == 0 && h->p.lattice != LB_D3Q19) fn = nullptr;
+  // the kernel addresses a row from its first node: rows must not straddle
+  // a block of the array layout
+  if (((int64_t(1) << h->L.lb) % h->L.px) != 0) fn = nullptr;
   const int64_t ny = h->p.ny, nz = h->p.nz;
   int64_t nzt = 0;
   bool ok = fn != nullptr;
