@@ -9,8 +9,13 @@ properties that hold at any size:
     mean, so the plane-averaged velocity profile equals the oracle's run on
     a 1 x 1 x 256 column started from the plane-averaged density;
   * D3Q27 third order 512^3 Taylor-Green: sampled nodes after 8 steps;
+  * D3Q19 256^3 channel after 12 steps (the fused step): whole z-columns
+    at sampled (x, y) against the oracle on each column's dependency cone
+    (periodic in x and y, walls in z);
   * two species 256^3 with 64 droplets: sampled interface nodes after 6
-    steps, and mass / momentum conservation over the full 5000 steps.
+    steps, mass / momentum conservation over the full 5000 steps, and the
+    FP32 run against the FP64 run of the same kernels over the full 5000
+    steps (the FP64 path is held to the oracle to 1e-9 on small cases).
 """
 import numpy as np
 import pytest
@@ -53,6 +58,46 @@ def test_channel_256_mean_profile_against_column_oracle():
     # the plane-mean dynamics are the column's up to products of the noise
     # (1e-4 squared), far below the FP32 bar
     assert err.max() <= 1e-5
+
+
+@pytest.mark.timeout(300)
+def test_channel_256_sampled_columns_against_oracle():
+    """The channel configuration, on the path the benchmark times (the fused
+    step), 12 steps: four whole z-columns (walls at both ends) against the
+    oracle on a 29 x 29 x 256 box around each (periodic in x and y: a node
+    after 12 steps depends on nodes within 12 links)."""
+    from paper_2304_06437_amd import lb
+
+    n, steps, tau, g = 256, 12, 0.6, 1e-6
+    shape = (n, n, n)
+    rho, u = inputs.channel_noise(n, n, n, 3)
+    p = make_params(lattice=19, shape=shape, tau=tau, force=(g, 0.0, 0.0), bc=(0, 0, 1))
+    with Simulation(p) as sim:
+        assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED
+        sim.init(rho, u)
+        sim.step(steps)
+        got = sim.moments(pineq=False, conserved=False)
+    h = steps + 2
+    w = 2 * h + 1
+    r3 = rho.reshape(n, n, n)
+    u3 = u.reshape(3, n, n, n)
+    worst_u = worst_rho = umax = 0.0
+    for (x, y) in ((0, 0), (255, 255), (128, 7), (3, 200)):
+        ix = np.arange(x - h, x + h + 1) % n
+        iy = np.arange(y - h, y + h + 1) % n
+        rb = r3[:, iy][:, :, ix].reshape(-1)
+        ub = u3[:, :, iy][:, :, :, ix].reshape(3, -1)
+        q = oracle.Params(lattice=19, nx=w, ny=w, nz=n, tau=tau, force=(g, 0.0, 0.0), bb=(0, 0, 1))
+        ref = oracle.simulate(q, rb, ub, steps)
+        col = h + w * h + w * w * np.arange(n)       # the box's centre column
+        gcol = x + n * y + n * n * np.arange(n)      # the same column in the domain
+        worst_u = max(worst_u, np.abs(got["u"][:, gcol] - ref["u"][:, col]).max())
+        worst_rho = max(worst_rho, np.abs(got["rho"][gcol] - ref["rho"][col]).max())
+        umax = max(umax, np.abs(ref["u"][:, col]).max())
+    print(f"256^3 channel, {steps} steps, 4 z-columns: max |du| {worst_u:.2e} (|u| up to "
+          f"{umax:.2e}), max |d rho| {worst_rho:.2e}")
+    assert umax > 1e-6
+    assert worst_u <= 1e-5 * umax and worst_rho <= 1e-7
 
 
 @pytest.mark.timeout(300)
@@ -163,3 +208,30 @@ def test_d3q27_third_order_1000_steps_error(d3q27_1000_reference, storage):
     err = max_rel(got["u"], ref["u"])
     print(f"D3Q27 order 3 40^3, 1000 steps, {storage}: max-rel u {err:.2e}")
     assert err <= (1e-5 if storage == "f32" else 0.1)
+
+
+@pytest.mark.timeout(400)
+def test_two_species_256_fp32_against_fp64_over_5000_steps():
+    """The full two-species configuration, 5000 steps, in FP32 and in FP64
+    (the FP64 path is held to the oracle to 1e-9 on small cases): the same
+    droplets in the same places.  Reported: velocity and phase differences;
+    held: the sign of phi (which phase a node belongs to) on all but a
+    1e-4 fraction of the nodes, the phase field within 0.05 everywhere, and
+    the velocity within 1e-2 of its largest value (measured 1.6e-3: the
+    spurious currents at the interfaces carry the FP32 rounding of the
+    colour split over the whole run)."""
+    n, steps = 256, 5000
+    _, rho, u, phi = _droplet_field(n, 64, 12.0)
+    out = {}
+    for storage in ("f64", "f32"):
+        p = make_params(lattice=19, shape=(n, n, n), tau=1.0, species=2, sigma=0.03, beta=0.7,
+                        storage=storage)
+        out[storage] = run(p, rho, u, steps, phi=phi, phi_out=True, pineq=False, conserved=False)
+    a, b = out["f32"], out["f64"]
+    umax = np.abs(b["u"]).max()
+    du = np.abs(a["u"] - b["u"]).max()
+    dphi = np.abs(a["phi"] - b["phi"]).max()
+    flips = np.mean(np.sign(a["phi"]) != np.sign(b["phi"]))
+    print(f"two species 256^3, {steps} steps, FP32 vs FP64: max |du| {du:.2e} (|u| up to "
+          f"{umax:.2e}), max |d phi| {dphi:.2e}, phase flips {flips:.2e}")
+    assert flips <= 1e-4 and dphi <= 0.05 and du <= 1e-2 * umax
