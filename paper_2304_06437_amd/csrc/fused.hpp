@@ -45,8 +45,8 @@
 // step's result is then invalid and the host reports an error), so every
 // wavefront ends.  The progress words count in epochs: a step reads the
 // epoch at its start, counts from epoch x stride, and the last wavefront
-// to finish advances the epoch, so no host value changes from step to step
-// and a captured launch can be replayed.
+// to finish advances the epoch, so every step is launched with the same
+// arguments and the words are never cleared between steps.
 #pragma once
 
 #include "kernels.hpp"

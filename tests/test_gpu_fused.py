@@ -228,3 +228,33 @@ def test_fused_wait_bound_gives_up_and_recovers():
             with pytest.raises(lb.LbError) as e:
                 lb.lb_set_fused_wait_limit(sim.handle, bad)
             assert e.value.status == lb.LB_EINVAL
+
+
+def test_fused_steps_of_two_handles_on_concurrent_streams():
+    """Two handles whose tiles each fill the device, stepping at the same
+    time on two streams: cooperative launches are not queued partly
+    resident, so no wait gives up and each result equals its run alone."""
+    p = make_params(lattice=19, shape=(512, 512, 16))
+    fields = [_fields(p, s) for s in (21, 22)]
+    alone = []
+    for rho, u in fields:
+        with Simulation(p) as sim:
+            assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED
+            sim.init(rho, u)
+            sim.step(10)
+            sim.synchronize()
+            alone.append(_pop_bytes(sim).clone())
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sims = [Simulation(p, stream=s) for s in streams]
+    for sim, (rho, u) in zip(sims, fields):
+        sim.init(rho, u)
+    torch.cuda.synchronize()
+    for _ in range(10):
+        for sim in sims:
+            sim.step(1)
+    statuses = [lb.load().lb_synchronize(sim.handle) for sim in sims]
+    print("statuses after concurrent fused steps:", statuses)
+    assert statuses == [lb.LB_OK, lb.LB_OK]
+    for sim, ref in zip(sims, alone):
+        assert torch.equal(_pop_bytes(sim), ref)
+        sim.close()
