@@ -185,9 +185,10 @@ int lb_step(lb_handle* h, int64_t nsteps);
 /* Enqueue one half of a time step: which = 0 the moments sweep (reads the
  * populations, writes the moment arrays), which = 1 the fused
  * stream-collide sweep (reads the moment arrays only, rewrites every
- * population in place).  lb_step(h, 1) is lb_sweep(h, 0) then
- * lb_sweep(h, 1); the step counter advances after which = 1.  For
- * instrumentation and for tests of the sweeps' data dependencies. */
+ * population in place).  lb_step(h, 1) on the two-sweep path is
+ * lb_sweep(h, 0) then lb_sweep(h, 1), and the fused step gives the same
+ * bits; the step counter advances after which = 1.  For instrumentation
+ * and for tests of the sweeps' data dependencies. */
 int lb_sweep(lb_handle* h, int which);
 /* (lb_init and lb_moments use the moment arrays as staging for their host
  * transfers: after them, run which = 0 before a which = 1 sweep.) */
