@@ -252,7 +252,10 @@ struct ImplT {
   static const void* fused_kernel(int v) {
     if constexpr (FUSED) {
       switch (v) {
-        case 8: return fused_fn<8>();
+        case 8:
+          // D3Q27 rows of 512 nodes do not fit one wavefront's registers
+          if constexpr (L::Q != 27) return fused_fn<8>();
+          break;
         case 4: return fused_fn<4>();
         case 2: return fused_fn<2>();
       }
