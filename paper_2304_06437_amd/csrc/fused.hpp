@@ -149,11 +149,12 @@ struct FusedSweep {
                            raw[a][h]);
   }
 
-  // Moments and post-collision coefficients of the lane's nodes.  The
-  // moments pass through an empty asm, as they pass through memory between
-  // the two sweeps: the coefficients are then computed from the rounded
-  // moments with the same instruction choices (no multiply shared with the
-  // moment computation, no FMA formed across the two).
+  // Moments and post-collision coefficients of the lane's nodes, with the
+  // two sweeps' arithmetic: node_moments and post_collision round every
+  // operation as written (no FMA contraction), so computing the
+  // coefficients straight from the moments in registers, with whatever
+  // values the compiler shares between the two, gives the bits that the
+  // two sweeps get through the moment arrays.
   __device__ __forceinline__ static void coef_of(const C (&raw)[Q][H][E], const StepParams<C>& p,
                                  C (&k)[H][E][K]) {
 #pragma unroll
@@ -164,8 +165,6 @@ struct FusedSweep {
 #pragma unroll
         for (int a = 0; a < Q; ++a) s[a] = raw[a][h][e];
         node_moments<L, C>(s, p, m);
-#pragma unroll
-        for (int q = 0; q < M; ++q) asm("" : "+v"(m[q]));
         post_collision<L, ORDER, C, FD>(m, p, k[h][e]);
       }
   }
