@@ -227,7 +227,10 @@ int lb_set_sweep_order(lb_handle* h, int order);
  * run this shape or tiling (the path is then unchanged), LB_EINVAL for a
  * bad path or z_tiles > nz.  A fused step that waits past its bound gives
  * up (its result is invalid): the next lb_synchronize, lb_moments or
- * lb_set_step_path call returns LB_EDEVICE once. */
+ * lb_set_step_path call returns LB_EDEVICE once.  The fused step is a
+ * cooperative launch; a caller that captures lb_step into a HIP graph
+ * should select the two-sweep path, whose launches are ordinary kernels
+ * (the batched entry points always use them). */
 #define LB_PATH_AUTO 0
 #define LB_PATH_TWO_SWEEP 1
 #define LB_PATH_FUSED 2
