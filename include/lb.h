@@ -74,9 +74,10 @@ enum lb_compute { LB_COMPUTE_F64 = 0, LB_COMPUTE_F32 = 1 };
 /* Problem statement (Sections 2-3).  Fill with lb_params_default first.
  * struct_size is the size of the caller's struct, so the layout can grow:
  * the library accepts sizeof(lb_params) and the sizes of its earlier
- * versions, LB_PARAMS_SIZE_V1 (up to `compute`) and LB_PARAMS_SIZE_V2 (up to
- * `wall_velocity`); fields beyond the caller's size take their defaults
- * (zero wall velocity, near-contact interactions off).  Any other size is
+ * versions, LB_PARAMS_SIZE_V1 (up to `compute`), LB_PARAMS_SIZE_V2 (up to
+ * `wall_velocity`) and LB_PARAMS_SIZE_V3 (up to the near-contact fields);
+ * fields beyond the caller's size take their defaults (zero wall velocity,
+ * near-contact interactions off, moment arrays kept).  Any other size is
  * LB_EINVAL. */
 typedef struct lb_params {
   size_t struct_size;     /* = sizeof(lb_params), or an earlier version's size */
@@ -125,11 +126,23 @@ typedef struct lb_params {
   double nci_eps;         /* bulk threshold, 0 < eps < 2 (default 0.1) */
   int32_t nci_reach;      /* sampling distance d, 1..8 lattice spacings (default 1) */
   int32_t nci_reserved_;  /* 0 */
+  /* Memory of the step (Section 4 counts the thread-safe method's arrays:
+   * Q populations + M moments per node).  1 (default): the moment arrays
+   * are allocated and both paths of lb_set_step_path are available.  0: the
+   * handle holds the population set only (D3Q19 FP32: 19 arrays, 76 B per
+   * node instead of 116) plus a bounded staging buffer for lb_init /
+   * lb_moments, and every step is the fused step, which keeps the moments
+   * in registers; the shape must have one (lb_set_step_path), else
+   * LB_EUNSUPPORTED.  Such a handle refuses the two-sweep path, lb_sweep
+   * and the batched entry points (LB_EUNSUPPORTED). */
+  int32_t keep_moments;
+  int32_t keep_moments_reserved_;  /* 0 */
 } lb_params;
 
 /* struct_size values of the earlier versions of lb_params. */
 #define LB_PARAMS_SIZE_V1 ((size_t)offsetof(lb_params, wall_velocity))
 #define LB_PARAMS_SIZE_V2 ((size_t)offsetof(lb_params, nci_strength))
+#define LB_PARAMS_SIZE_V3 ((size_t)offsetof(lb_params, keep_moments))
 
 typedef struct lb_handle lb_handle;
 
@@ -139,14 +152,16 @@ typedef struct lb_handle lb_handle;
 void lb_params_default(lb_params* p);
 
 /* Exact number of device bytes lb_create needs for these parameters:
- * populations (species * Q arrays) + moments (M arrays) of npad nodes each,
- * + npad bytes of near-contact flags when nci_strength > 0,
+ * populations (species * Q arrays) + moments (M arrays) of npad nodes each
+ * (with keep_moments 0, in place of the moments, a staging buffer of at most
+ * 256 MiB), + npad bytes of near-contact flags when nci_strength > 0,
  * npad = px * ny * nz rounded up to the layout's block size, where the row
  * pitch px is nx rounded up to a multiple of the stream-collide sweep's
  * vector chunk (1 to 8 nodes; see lb_layout), each region 256-byte aligned,
- * + 64 KiB of FP64 reduction scratch (Section 4 counts 15 arrays per node
- * for D2Q9 and 29 for D3Q19 in single precision).  Returns 0 for invalid
- * parameters. */
+ * + npad bytes of reference colours for two species, + 64 KiB of FP64
+ * reduction scratch, + ny * nz + 3 32-bit progress words where the shape has
+ * a fused step (Section 4 counts 15 arrays per node for D2Q9 and 29 for
+ * D3Q19 in single precision).  Returns 0 for invalid parameters. */
 size_t lb_required_bytes(const lb_params* p);
 
 /* Validate parameters without touching the device. */
@@ -154,7 +169,8 @@ int lb_validate(const lb_params* p);
 
 /* Create a simulation on the current HIP device: the single population set
  * per species and the moment arrays the method needs (Section 4 counts the
- * arrays per node; Section 3: no second population set).
+ * arrays per node; Section 3: no second population set), or with
+ * keep_moments 0 the population set alone.
  *   dev_mem    device buffer of dev_bytes >= lb_required_bytes(p), 256-byte
  *              aligned, owned by the caller and outliving the handle; or
  *              NULL, in which case the library allocates (hipMalloc) and
@@ -162,8 +178,9 @@ int lb_validate(const lb_params* p);
  *   hip_stream hipStream_t to enqueue all work on (borrowed, may be NULL for
  *              the null stream).
  * LB_ENOMEM if dev_bytes is too small or the allocation fails, LB_EINVAL for
- * a misaligned dev_mem.  The populations are zero (rest state) until
- * lb_init. */
+ * a misaligned dev_mem, LB_EUNSUPPORTED for keep_moments 0 where the device
+ * cannot run this shape's fused step.  The populations are zero (rest
+ * state) until lb_init. */
 int lb_create(const lb_params* p, void* dev_mem, size_t dev_bytes, void* hip_stream,
               lb_handle** out);
 
@@ -188,7 +205,8 @@ int lb_step(lb_handle* h, int64_t nsteps);
  * population in place).  lb_step(h, 1) on the two-sweep path is
  * lb_sweep(h, 0) then lb_sweep(h, 1), and the fused step gives the same
  * bits; the step counter advances after which = 1.  For instrumentation
- * and for tests of the sweeps' data dependencies. */
+ * and for tests of the sweeps' data dependencies.  LB_EUNSUPPORTED for a
+ * handle without moment arrays (keep_moments 0). */
 int lb_sweep(lb_handle* h, int which);
 /* (lb_init and lb_moments use the moment arrays as staging for their host
  * transfers: after them, run which = 0 before a which = 1 sweep.) */
@@ -230,7 +248,9 @@ int lb_set_sweep_order(lb_handle* h, int order);
  * lb_set_step_path call returns LB_EDEVICE once.  The fused step is a
  * cooperative launch; a caller that captures lb_step into a HIP graph
  * should select the two-sweep path, whose launches are ordinary kernels
- * (the batched entry points always use them). */
+ * (the batched entry points always use them).  A handle without moment
+ * arrays (keep_moments 0) has the fused path only: LB_PATH_AUTO and
+ * LB_PATH_FUSED select it, LB_PATH_TWO_SWEEP is LB_EUNSUPPORTED. */
 #define LB_PATH_AUTO 0
 #define LB_PATH_TWO_SWEEP 1
 #define LB_PATH_FUSED 2
@@ -314,7 +334,8 @@ typedef struct lb_batch lb_batch;
 int lb_batch_create(void* hip_stream, lb_batch** out);
 
 /* Advance handles[i] by nsteps[i] >= 0 steps (distinct handles, count >= 0;
- * LB_EUNSUPPORTED for a handle with near-contact interactions on).
+ * LB_EUNSUPPORTED for a handle with near-contact interactions on or without
+ * moment arrays).
  * Handles with the same kernel configuration (lattice, Hermite order,
  * species, storage, compute, row vector width) share one moments launch and
  * one stream-collide launch per step; a handle whose step count is reached

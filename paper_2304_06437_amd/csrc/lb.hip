@@ -17,7 +17,8 @@
 // starts 256-byte aligned and the moments sweep needs no tail.
 // lb_init and lb_moments stage their host transfers through m, which the
 // next step's moments sweep rewrites anyway; the library allocates nothing
-// beyond lb_required_bytes on the device.
+// beyond lb_required_bytes on the device.  A handle without moment arrays
+// (keep_moments 0, fused step only) keeps a bounded m for that staging alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +58,8 @@ constexpr size_t kAlign = 256;
 // Host transfers of lb_init / lb_moments move at most this many nodes per
 // chunk, so their host staging buffer stays bounded (<= 1.2 GB).
 constexpr int64_t kMaxStageNodes = int64_t(1) << 24;
+// A handle without moment arrays keeps at most this much staging memory.
+constexpr size_t kStageBytes = size_t(256) << 20;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -82,7 +85,9 @@ int lattice_q(int lattice) {
 bool normalize(const lb_params* in, lb_params* out) {
   if (!in) return false;
   const size_t sz = in->struct_size;
-  if (sz != sizeof(lb_params) && sz != LB_PARAMS_SIZE_V2 && sz != LB_PARAMS_SIZE_V1) return false;
+  if (sz != sizeof(lb_params) && sz != LB_PARAMS_SIZE_V3 && sz != LB_PARAMS_SIZE_V2 &&
+      sz != LB_PARAMS_SIZE_V1)
+    return false;
   lb_params_default(out);
   std::memcpy(out, in, sz);
   if (sz < sizeof(lb_params)) {
@@ -95,6 +100,7 @@ bool normalize(const lb_params* in, lb_params* out) {
 }
 
 int validate_full(const lb_params* p);
+int fused_rows(const lb_params* p);
 
 int validate(const lb_params* in) {
   lb_params p;
@@ -163,6 +169,9 @@ int validate_full(const lb_params* p) {
   // keep every index comfortably inside int64
   const double N = (double)p->nx * (double)p->ny * (double)p->nz;
   if (N > 4.0e12) return LB_EINVAL;
+  // population set only: every step is the fused step
+  if (p->keep_moments != 0 && p->keep_moments != 1) return LB_EINVAL;
+  if (p->keep_moments == 0 && fused_rows(p) == 0) return LB_EUNSUPPORTED;
   return LB_OK;
 }
 
@@ -222,7 +231,10 @@ Layout layout_of(const lb_params* p) {
   L.npad = (ns + B - 1) / B * B;
   L.f_off = 0;
   L.m_off = align_up((size_t)L.species * L.Q * L.npad * L.ssize, kAlign);
-  L.n_off = L.m_off + align_up((size_t)L.M * L.npad * L.csize, kAlign);
+  // the moment arrays, or (population set only) just the staging buffer of
+  // lb_init / lb_moments
+  const size_t mbytes = (size_t)L.M * L.npad * L.csize;
+  L.n_off = L.m_off + align_up(p->keep_moments ? mbytes : std::min(mbytes, kStageBytes), kAlign);
   const bool nci = p->species == 2 && p->nci_strength > 0.0;
   L.c_off = L.n_off + (nci ? align_up((size_t)L.npad, kAlign) : 0);
   L.r_off = L.c_off + (p->species == 2 ? align_up((size_t)L.npad, kAlign) : 0);
@@ -399,6 +411,7 @@ void lb_params_default(lb_params* p) {
   p->nci_strength = 0.0;
   p->nci_eps = 0.1;
   p->nci_reach = 1;
+  p->keep_moments = 1;
 }
 
 int lb_validate(const lb_params* p) { return validate(p); }
@@ -479,7 +492,7 @@ int lb_create(const lb_params* in, void* dev_mem, size_t dev_bytes, void* hip_st
       return status_of(e);
     }
     h->fv = fused_rows(p);
-    const int fs = configure_fused(h, 0, 0);
+    const int fs = configure_fused(h, p->keep_moments ? 0 : 2, 0);
     if (fs != LB_OK) {
       if (h->owned) (void)hipFree(h->base);
       delete h;
@@ -512,7 +525,7 @@ int lb_init(lb_handle* h, const double* rho, const double* u, const double* phi)
   }
   try {
     const int per = 1 + L.D + (two ? 1 : 0);  // doubles staged per node
-    const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
+    const int64_t cap = (int64_t)((L.n_off - L.m_off) / (per * sizeof(double)));
     const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
     // uninitialised: every element staged is written before it is copied
     std::unique_ptr<double[]> hb(new double[(size_t)per * chunk]);
@@ -557,6 +570,7 @@ int lb_step(lb_handle* h, int64_t nsteps) {
 
 int lb_sweep(lb_handle* h, int which) {
   if (!h || (which != 0 && which != 1)) return LB_EINVAL;
+  if (!h->p.keep_moments) return LB_EUNSUPPORTED;
   if (which == 0) LB_TRY_HIP(h->impl->moments(h));
   else {
     LB_TRY_HIP(h->impl->stream_collide(h));
@@ -579,6 +593,10 @@ int lb_set_sweep_order(lb_handle* h, int order) {
 
 int lb_set_step_path(lb_handle* h, int path, int64_t z_tiles) {
   if (!h || path < 0 || path > 2 || z_tiles < 0) return LB_EINVAL;
+  if (!h->p.keep_moments) {
+    if (path == 1) return LB_EUNSUPPORTED;
+    path = 2;  // the only path of a handle without moment arrays
+  }
   // drain: the progress words are reset below
   LB_TRY_HIP(hipStreamSynchronize(h->stream));
   const int st = fused_status(h);
@@ -652,7 +670,7 @@ int lb_moments(lb_handle* h, double* rho, double* u, double* pineq, double* phi,
   if (!two) phi = nullptr;
   try {
     if (rho || u || pineq || phi) {
-      const int64_t cap = (int64_t)((size_t)L.M * L.npad * L.csize / (per * sizeof(double)));
+      const int64_t cap = (int64_t)((L.n_off - L.m_off) / (per * sizeof(double)));
       const int64_t chunk = std::min(std::min(cap, kMaxStageNodes), N);
       double* stage = (double*)h->m;
       // staged rows: rho, u (D), Pi^neq (K), phi; only the requested ones
@@ -903,7 +921,7 @@ int lb_batch_step(lb_batch* b, lb_handle* const* hs, const int64_t* nsteps, int 
   }
   // the batched sweeps have no near-contact flag pass
   for (int i = 0; i < count; ++i)
-    if (hs[i]->nci) return LB_EUNSUPPORTED;
+    if (hs[i]->nci || !hs[i]->p.keep_moments) return LB_EUNSUPPORTED;
   if (count == 0) return LB_OK;
   try {
     // segments of constant active set: jobs sorted by their step counts
@@ -1183,7 +1201,7 @@ int lb_step_batch_noalloc(lb_handle* const* hs, const int64_t* nsteps, int count
       if (hs[k] == hs[i]) return LB_EINVAL;
   }
   for (int i = 0; i < count; ++i)
-    if (hs[i]->nci) return LB_EUNSUPPORTED;
+    if (hs[i]->nci || !hs[i]->p.keep_moments) return LB_EUNSUPPORTED;
   int cur = -1;
   LB_TRY_HIP(hipGetDevice(&cur));
   if (cur != hs[0]->device) return LB_EINVAL;

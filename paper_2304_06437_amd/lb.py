@@ -50,12 +50,15 @@ class lb_params(ctypes.Structure):
         ("nci_eps", ctypes.c_double),
         ("nci_reach", ctypes.c_int32),
         ("nci_reserved_", ctypes.c_int32),
+        ("keep_moments", ctypes.c_int32),
+        ("keep_moments_reserved_", ctypes.c_int32),
     ]
 
 
 # struct_size of the earlier versions of lb_params (include/lb.h)
 LB_PARAMS_SIZE_V1 = lb_params.wall_velocity.offset
 LB_PARAMS_SIZE_V2 = lb_params.nci_strength.offset
+LB_PARAMS_SIZE_V3 = lb_params.keep_moments.offset
 
 
 class LbError(RuntimeError):

@@ -13,14 +13,16 @@ from . import lb
 
 def make_params(lattice=19, shape=(32, 32, 32), tau=0.6, rho0=1.0, force=(0.0, 0.0, 0.0),
                 bc=(0, 0, 0), order=2, storage="f32", species=1, sigma=0.0, beta=0.0,
-                wall_velocity=None, nci_strength=0.0, nci_eps=0.1, nci_reach=1):
+                wall_velocity=None, nci_strength=0.0, nci_eps=0.1, nci_reach=1, keep_moments=1):
     """lb_params for a problem; wall_velocity[axis][low, high][component]
     gives moving walls on bounce-back faces; nci_* the near-contact
-    interactions of two species."""
+    interactions of two species; keep_moments=0 holds the population set
+    only (fused step only)."""
     st = lb.STORAGE[storage] if isinstance(storage, str) else int(storage)
     compute = lb.LB_COMPUTE_F64 if st == lb.LB_STORE_F64 else lb.LB_COMPUTE_F32
     kw = {} if wall_velocity is None else dict(wall_velocity=wall_velocity)
-    kw.update(nci_strength=nci_strength, nci_eps=nci_eps, nci_reach=nci_reach)
+    kw.update(nci_strength=nci_strength, nci_eps=nci_eps, nci_reach=nci_reach,
+              keep_moments=keep_moments)
     return lb.lb_params_default(lattice=lattice, nx=shape[0], ny=shape[1], nz=shape[2], tau=tau,
                                 rho0=rho0, force=tuple(force), bc=tuple(bc),
                                 hermite_order=order, storage=st, compute=compute,

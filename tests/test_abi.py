@@ -259,10 +259,11 @@ def test_params_struct_versions():
     """Callers built against the earlier, shorter lb_params (no moving walls;
     no near-contact fields) are accepted; unknown sizes are not."""
     import ctypes
-    assert lb.LB_PARAMS_SIZE_V1 < lb.LB_PARAMS_SIZE_V2 < ctypes.sizeof(lb.lb_params)
+    assert (lb.LB_PARAMS_SIZE_V1 < lb.LB_PARAMS_SIZE_V2 < lb.LB_PARAMS_SIZE_V3
+            < ctypes.sizeof(lb.lb_params))
     full = lb.lb_params_default(lattice=19, nx=24, ny=20, nz=16)
     want = lb.lb_required_bytes(full)
-    for size in (lb.LB_PARAMS_SIZE_V1, lb.LB_PARAMS_SIZE_V2):
+    for size in (lb.LB_PARAMS_SIZE_V1, lb.LB_PARAMS_SIZE_V2, lb.LB_PARAMS_SIZE_V3):
         p = lb.lb_params_default(lattice=19, nx=24, ny=20, nz=16)
         # the tail beyond the caller's size is garbage the library must not read
         raw = (ctypes.c_ubyte * ctypes.sizeof(lb.lb_params)).from_buffer(p)
@@ -276,6 +277,34 @@ def test_params_struct_versions():
         p.struct_size = bad
         assert lb.lb_validate(p) == lb.LB_EINVAL
         assert lb.lb_required_bytes(p) == 0
+
+
+def test_population_set_only_parameters():
+    """keep_moments 0: the population set alone plus a staging buffer of at
+    most 256 MiB in place of the moment arrays (Section 4's count without
+    the M moments), only for shapes with a fused step."""
+    assert lb.lb_params_default().keep_moments == 1
+    for v in (-1, 2):
+        assert lb.lb_validate(lb.lb_params_default(nx=128, keep_moments=v)) == lb.LB_EINVAL
+    for kw in (dict(lattice=9, nx=128, ny=64, nz=1), dict(nx=96), dict(nx=1024),
+               dict(nx=128, storage=lb.LB_STORE_F64, compute=lb.LB_COMPUTE_F64),
+               dict(nx=128, species=2, sigma=0.03, beta=0.7)):
+        p = lb.lb_params_default(keep_moments=0, **kw)
+        assert lb.lb_validate(p) == lb.LB_EUNSUPPORTED, kw
+        assert lb.lb_required_bytes(p) == 0, kw
+    al = lambda v: -(-v // 256) * 256
+    for (nx, ny, nz, st, ss) in ((128, 24, 20, lb.LB_STORE_F32, 4),
+                                 (256, 40, 33, lb.LB_STORE_F16S, 2),
+                                 (512, 512, 512, lb.LB_STORE_F32, 4)):
+        kw = dict(lattice=19, nx=nx, ny=ny, nz=nz, storage=st)
+        full, B, npad = _blocked_bytes(19, 10, nx * ny * nz, ss, 4, rows=ny * nz)
+        assert lb.lb_required_bytes(lb.lb_params_default(**kw)) == full
+        lean = lb.lb_required_bytes(lb.lb_params_default(keep_moments=0, **kw))
+        stage = min(10 * npad * 4, 256 << 20)
+        assert lean == full - al(10 * npad * 4) + al(stage), (nx, ny, nz)
+    # D3Q19 FP32 at 512^3: 76 B per node plus the bounded staging buffer
+    # (29 arrays of 4 B with the moments)
+    assert abs(lean / 512 ** 3 - 76) < 2.1 and abs(full / 512 ** 3 - 116) < 0.1
 
 
 def test_near_contact_parameters():

@@ -187,11 +187,20 @@ def test_fused_full_size_equals_two_sweeps():
         lb.lb_set_step_path(sim.handle, path, 0)
         sim.init(rho, u)
         sims.append(sim)
+    # and a handle holding the population set alone (76 B per node)
+    lean = Simulation(make_params(lattice=19, shape=(n, n, n), tau=0.55, keep_moments=0))
+    lean.init(rho, u)
+    sims.append(lean)
+    print(f"device bytes: {sims[0].nbytes / n ** 3:.2f} per node with moment arrays, "
+          f"{lean.nbytes / n ** 3:.2f} without")
+    assert lean.nbytes < 0.68 * sims[0].nbytes  # 76 B of 116, plus 256 MiB of staging
     assert lb.lb_get_step_path(sims[0].handle)[0] == lb.LB_PATH_FUSED
+    assert lb.lb_get_step_path(lean.handle) == lb.lb_get_step_path(sims[0].handle)
     for sim in sims:
         sim.step(3)
         sim.synchronize()
     assert torch.equal(_pop_bytes(sims[0]), _pop_bytes(sims[1]))
+    assert torch.equal(_pop_bytes(lean), _pop_bytes(sims[1]))
     for sim in sims:
         sim.close()
 
@@ -258,3 +267,73 @@ def test_fused_steps_of_two_handles_on_concurrent_streams():
     for sim, ref in zip(sims, alone):
         assert torch.equal(_pop_bytes(sim), ref)
         sim.close()
+
+
+# name: (make_params keywords, steps) of handles without moment arrays
+LEAN_CASES = {
+    "d3q19_128_walls_force": (dict(lattice=19, shape=(128, 12, 20), bc=(0, 1, 1),
+                                   force=(1e-5, 0.0, 2e-6)), 7),
+    "d3q19_256_f16s": (dict(lattice=19, shape=(256, 6, 10), storage="f16s"), 6),
+    "d3q27_o3_128": (dict(lattice=27, shape=(128, 6, 8), order=3), 5),
+    # moment arrays of 10 x 8.4e6 nodes: the 256 MiB staging buffer moves
+    # lb_init and lb_moments in several chunks
+    "d3q19_256x256x128_bounded_staging": (dict(lattice=19, shape=(256, 256, 128)), 3),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LEAN_CASES))
+def test_population_set_only_equals_full_handle(case):
+    """keep_moments 0: a handle holding the population set alone steps with
+    the fused step byte for byte like a handle with moment arrays on the
+    two-sweep path, and reads the same moments and conserved sums back."""
+    kw, steps = LEAN_CASES[case]
+    full = make_params(**kw)
+    rho, u = _fields(full, len(case))
+    with Simulation(full) as a, Simulation(make_params(keep_moments=0, **kw)) as b:
+        # small shapes: the staging buffer is as large as the moment arrays
+        assert b.nbytes < a.nbytes if case.endswith("staging") else b.nbytes <= a.nbytes
+        lb.lb_set_step_path(a.handle, lb.LB_PATH_TWO_SWEEP, 0)
+        path, zt = lb.lb_get_step_path(b.handle)
+        assert path == lb.LB_PATH_FUSED and zt >= 1
+        for sim in (a, b):
+            sim.init(rho, u)
+            sim.step(steps)
+            sim.synchronize()
+        diff = int((_pop_bytes(a) != _pop_bytes(b)).sum().item())
+        print(f"{case}: {steps} steps, {zt} runs per row, {b.nbytes} bytes against "
+              f"{a.nbytes}, {diff} differing bytes")
+        assert diff == 0
+        ma = a.moments(conserved=True)
+        mb = b.moments(conserved=True)
+        for key in ("rho", "u", "pineq", "conserved"):
+            assert np.array_equal(ma[key], mb[key]), key
+
+
+def test_population_set_only_refusals():
+    """Without moment arrays there is no two-sweep step: lb_sweep, the
+    two-sweep path and the batched entry points are refused; a shape whose
+    tiles cannot all be resident is refused at creation."""
+    p = make_params(lattice=19, shape=(128, 8, 8), keep_moments=0)
+    rho, u = _fields(p, 9)
+    with Simulation(p) as sim:
+        sim.init(rho, u)
+        assert lb.lb_get_step_path(sim.handle)[0] == lb.LB_PATH_FUSED
+        calls = (lambda: lb.lb_sweep(sim.handle, 0), lambda: lb.lb_sweep(sim.handle, 1),
+                 lambda: lb.lb_set_step_path(sim.handle, lb.LB_PATH_TWO_SWEEP, 0),
+                 lambda: lb.lb_step_batch([sim.handle], [1]),
+                 lambda: lb.lb_step_batch_noalloc([sim.handle], [1]))
+        for call in calls:
+            with pytest.raises(lb.LbError) as e:
+                call()
+            assert e.value.status == lb.LB_EUNSUPPORTED
+        # the automatic path is the fused one
+        lb.lb_set_step_path(sim.handle, lb.LB_PATH_AUTO, 2)
+        assert lb.lb_get_step_path(sim.handle) == (lb.LB_PATH_FUSED, 2)
+        assert lb.lb_step_count(sim.handle) == 0  # nothing stepped
+        sim.step(4)
+        sim.synchronize()
+        assert lb.lb_step_count(sim.handle) == 4
+    tall = make_params(lattice=19, shape=(128, 40000, 2), keep_moments=0)
+    with pytest.raises(lb.LbError) as e:
+        Simulation(tall)
+    assert e.value.status == lb.LB_EUNSUPPORTED
