@@ -127,19 +127,46 @@ __device__ __forceinline__ void node_moments(const C (&s)[L::Q], const StepParam
 #pragma unroll
     for (int be = 0; be < D; ++be) P[al][be] = C(0);
   }
+  if constexpr (D == 3) {
+    // opposite links a, a' (c_a' = -c_a) enter every first moment with
+    // opposite signs and every second moment with the same sign: sum their
+    // difference and their sum once (54 additions per D3Q19 node instead
+    // of 90)
 #pragma unroll
-  for (int a = 1; a < L::Q; ++a) {
-    drho += s[a];
+    for (int a = 1; a < L::Q; ++a) {
+      const int b = opposite<L>(a);
+      if (b < a) continue;
+      const C sp = s[a] + s[b];
+      const C dp = s[a] - s[b];
+      drho += sp;
 #pragma unroll
-    for (int al = 0; al < D; ++al) {
-      if (L::c[a][al] > 0) j[al] += s[a];
-      if (L::c[a][al] < 0) j[al] -= s[a];
-      if (L::c[a][al] != 0) P[al][al] += s[a];
+      for (int al = 0; al < D; ++al) {
+        if (L::c[a][al] > 0) j[al] += dp;
+        if (L::c[a][al] < 0) j[al] -= dp;
+        if (L::c[a][al] != 0) P[al][al] += sp;
 #pragma unroll
-      for (int be = al + 1; be < D; ++be) {
-        const int cc = L::c[a][al] * L::c[a][be];
-        if (cc > 0) P[al][be] += s[a];
-        if (cc < 0) P[al][be] -= s[a];
+        for (int be = al + 1; be < D; ++be) {
+          const int cc = L::c[a][al] * L::c[a][be];
+          if (cc > 0) P[al][be] += sp;
+          if (cc < 0) P[al][be] -= sp;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int a = 1; a < L::Q; ++a) {
+      drho += s[a];
+#pragma unroll
+      for (int al = 0; al < D; ++al) {
+        if (L::c[a][al] > 0) j[al] += s[a];
+        if (L::c[a][al] < 0) j[al] -= s[a];
+        if (L::c[a][al] != 0) P[al][al] += s[a];
+#pragma unroll
+        for (int be = al + 1; be < D; ++be) {
+          const int cc = L::c[a][al] * L::c[a][be];
+          if (cc > 0) P[al][be] += s[a];
+          if (cc < 0) P[al][be] -= s[a];
+        }
       }
     }
   }
