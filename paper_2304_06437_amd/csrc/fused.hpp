@@ -72,12 +72,6 @@ __device__ __forceinline__ void sync_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int64_t uniform64(int64_t v) {
-  const uint64_t u = (uint64_t)v;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
 
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD>
 struct FusedSweep {

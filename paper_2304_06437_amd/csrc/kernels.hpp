@@ -91,6 +91,25 @@ __device__ __forceinline__ int64_t astride(const StepParams<C>& p) {
   return int64_t(1) << p.lb;
 }
 
+// A value the same in every lane of the wavefront, so marked for the
+// compiler (scalar registers and scalar arithmetic for what derives from it).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// p + a 32-bit byte offset (a lane's offset from a wave-uniform base).
+template <typename T>
+__device__ __forceinline__ T* at_bytes(T* p, uint32_t bytes) {
+  return (T*)((char*)p + bytes);
+}
+template <typename T>
+__device__ __forceinline__ const T* at_bytes(const T* p, uint32_t bytes) {
+  return (const T*)((const char*)p + bytes);
+}
+
 // Storage node of lattice node n = x + nx (y + ny z).  Rows are px >= nx
 // storage nodes apart, so that every row starts on a vector boundary; nodes
 // x in [nx, px) of a row are padding: zero populations (the stream-collide
@@ -476,9 +495,13 @@ static_assert(row_order_is_permutation<D3Q27>(), "D3Q27 row order");
 // node (position tl < E - 1) reads padding moments and stores zeros into
 // the padding populations.  PAD selects that handling at compile time: the
 // PAD = false variant (fewer instructions per link) requires px == nx.
+// RB = true requires every row to lie inside one block of the array layout
+// (px divides the block size B): then element (a, row start + x) is
+// slot(row start) + a B + x, a wave-uniform base (scalar arithmetic) plus a
+// 32-bit lane offset, instead of a 64-bit slot computation per lane and link.
 // -------------------------------------------------------------------------
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false,
-          bool PAD = true>
+          bool PAD = true, bool RB = false>
 struct StreamCollide {
   using ML = MomentLayout<L>;
   using CL = CoefLayout<L, ORDER>;
@@ -490,6 +513,7 @@ struct StreamCollide {
     int64_t xh[H];    // first node of this lane's chunk h
     bool act[H];      // chunk h starts inside the row
     int tl[H];        // position of the row's last node x = nx - 1 in chunk h, E if absent
+    uint32_t bs[H];   // RB: byte offset of chunk h's first node from its row's slot (S)
     int64_t y, z, rowbase;
   };
 
@@ -544,7 +568,9 @@ struct StreamCollide {
               if (e == tl) val[e] = rv;
           }
         }
-        S* dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
+        S* dst;
+        if constexpr (RB) dst = at_bytes(f + slot<L::Q>(p, trow) + A * astride(p), ln.bs[h]);
+        else dst = f + slot<L::Q>(p, trow + xs) + A * astride(p);
         const bool cut_lo = (cx > 0) && p.bbx && (xs == 0);   // source x = -1
         const bool cut_hi = (cx < 0) && p.bbx && (tl < E);    // source x = nx
         if (!(cut_lo || cut_hi)) {
@@ -592,7 +618,10 @@ struct StreamCollide {
           for (int e = 1; e < E; ++e)
             if (e > tl) bv[e] = C(0);
         }
-        store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
+        if constexpr (RB)
+          store_pack<S, C, E>(at_bytes(f + slot<L::Q>(p, ln.rowbase) + AB * astride(p), ln.bs[h]), bv);
+        else
+          store_pack<S, C, E>(f + slot<L::Q>(p, ln.rowbase + xs) + AB * astride(p), bv);
       }
       if constexpr (cx != 0) {
         if (row_in && p.bbx) {
@@ -656,6 +685,7 @@ struct StreamCollide {
       ln.act[h] = ln.xh[h] < p.nx;
       const int64_t rem = p.nx - 1 - ln.xh[h];
       ln.tl[h] = (rem >= 0 && rem < E) ? (int)rem : E;
+      ln.bs[h] = (uint32_t)(x0 + h * 64 * E + lane * E) * (uint32_t)sizeof(S);
     }
 
     C own[H][E][K];
@@ -666,7 +696,14 @@ struct StreamCollide {
 #pragma unroll
         for (int q = 0; q < M; ++q) {
           if (ln.act[h]) {
-            load_plain<C, E, false>(m + slot<M>(p, ln.rowbase + ln.xh[h]) + q * astride(p), mv[h][q]);
+            if constexpr (RB)
+              load_plain<C, E, false>(
+                  at_bytes(m + slot<M>(p, ln.rowbase) + q * astride(p),
+                           (uint32_t)(ln.bs[h] / sizeof(S) * sizeof(C))),
+                  mv[h][q]);
+            else
+              load_plain<C, E, false>(m + slot<M>(p, ln.rowbase + ln.xh[h]) + q * astride(p),
+                                      mv[h][q]);
           } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) mv[h][q][e] = C(0);
@@ -743,12 +780,13 @@ __device__ __forceinline__ int64_t ordered_unit(const StepParams<C>& p, int64_t 
 }
 
 template <class L, int ORDER, typename S, typename C, int E, int H, bool FD = false,
-          bool PAD = true>
+          bool PAD = true, bool RB = false>
 __global__ __launch_bounds__(256) void k_stream_collide(const C* __restrict__ m,
                                                         S* __restrict__ f, StepParams<C> p) {
-  const int64_t w = flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  StreamCollide<L, ORDER, S, C, E, H, FD, PAD>::run_wave(m, f, p,
-                                                         ordered_unit(p, w, p.nseg * p.ny * p.nz));
+  int64_t w = flat_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if constexpr (RB) w = uniform64(w);  // the row base in scalar registers
+  StreamCollide<L, ORDER, S, C, E, H, FD, PAD, RB>::run_wave(
+      m, f, p, ordered_unit(p, w, p.nseg * p.ny * p.nz));
 }
 
 // -------------------------------------------------------------------------
