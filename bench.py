@@ -21,6 +21,10 @@ recorded on the launch stream during the timed region.  The HBM traffic
 counters (FETCH_SIZE / WRITE_SIZE) come from separate rocprofv3 runs kept
 under profiles/; they are reported only while the kernel source they were
 taken on is unchanged.
+
+Memory: the handle's device footprint (lb_required_bytes) per node, and
+the footprint of a handle holding the population set alone (keep_moments =
+0, fused step only) where the shape has a fused step.
 """
 from __future__ import annotations
 
@@ -322,6 +326,16 @@ def main():
     if w["species"] == 2:
         kw.update(sigma=0.03, beta=0.7)
     params = make_params(**kw)
+    # device footprint, and without moment arrays where the shape has a fused
+    # step (lb_params.keep_moments = 0: the population set alone)
+    lean = make_params(keep_moments=0, **kw)
+    memory = {"device_bytes": lb.lb_required_bytes(params),
+              "bytes_per_node": round(lb.lb_required_bytes(params) / N, 2),
+              "population_set_only": None}
+    if lb.lb_validate(lean) == lb.LB_OK:
+        memory["population_set_only"] = {
+            "device_bytes": lb.lb_required_bytes(lean),
+            "bytes_per_node": round(lb.lb_required_bytes(lean) / N, 2)}
     rho, u, phi = workload_fields(w, n)
     copies = copy_ceilings(torch) if not args.no_copy else None
 
@@ -402,6 +416,7 @@ def main():
             "storage": args.storage, "compute": "f32", "bytes_per_update": b_update,
             "path": "fused" if fused else "two_sweep", "z_tiles": z_tiles,
         },
+        "memory": memory,
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
