@@ -53,6 +53,11 @@ CASES = {
     "d3q27_o2_128": (dict(lattice=27, shape=(128, 6, 8)), 2, 5),
     "d3q27_o3_256_walls": (dict(lattice=27, shape=(256, 5, 6), order=3, bc=(0, 1, 1)), 2, 5),
     "d3q27_o3_128_f16s": (dict(lattice=27, shape=(128, 6, 6), order=3, storage="f16s"), 3, 5),
+    "d3q27_o3_128_f16s_walls_x": (dict(lattice=27, shape=(128, 6, 6), order=3, storage="f16s",
+                                       bc=(1, 0, 0)), 3, 5),
+    "d3q27_o3_128_moving_walls": (dict(lattice=27, shape=(128, 8, 6), order=3, bc=(1, 1, 1),
+                                       wall_velocity=_lid(0, 1, 1, 0.03) + _lid(2, 0, 0, 0.02)),
+                                  2, 5),
 }
 
 

@@ -41,6 +41,11 @@ CASES = {
                             2, (0, 0, 0)),
     "box_d3q27_order3": (27, (70, 14, 12), 0.65, 300, (0, 1, 1),
                          dict(y0=(0.04, 0, 0.01), z1=(-0.03, 0.02, 0)), 3, (0, 0, 0)),
+    # rows of 64 nodes inside one layout block (row-base addressing), moving
+    # walls on every axis
+    "box_d3q27_order3_rows64": (27, (64, 10, 8), 0.65, 300, (1, 1, 1),
+                                dict(x0=(0, 0.02, 0.01), y1=(0.04, 0, 0.01), z0=(-0.03, 0.02, 0)),
+                                3, (0, 0, 0)),
 }
 
 

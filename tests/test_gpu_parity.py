@@ -71,6 +71,10 @@ CASES = {
     "column_z_walls_d3q19": (19, (1, 1, 32), 0.8, 1000, "channel", (1e-5, 0, 0), (0, 0, 1), 2),
     "single_node_d3q19": (19, (1, 1, 1), 0.7, 20, "random", (1e-4, 0, 0), (0, 0, 0), 2),
     "plane_y1_d3q27": (27, (33, 1, 5), 0.7, 100, "random", (0, 0, 0), (0, 0, 1), 3),
+    # rows of 64 nodes inside one layout block: the D3Q27 sweep addressing
+    # rows from a wave-uniform base, with x walls cutting its vectors
+    "walls_xz_d3q27_order3_rows64": (27, (64, 6, 8), 0.65, 200, "random", (0, 1e-5, 0),
+                                     (1, 0, 1), 3),
 }
 
 
