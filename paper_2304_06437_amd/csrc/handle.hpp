@@ -296,21 +296,46 @@ struct ImplT {
   }
 };
 
+// Lane vectors per lattice and storage type: FP32 2 x 2 nodes per lane (4 x
+// 1 for D3Q27); 16-bit storage one 16-byte chunk of 8 nodes (4 x 1 for
+// D3Q27).  The 32/64-bit and the 16-bit storage types are instantiated by
+// separate functions, so that the heavy lattices build them in separate
+// translation units (which the build compiles in parallel).
+template <class L>
+struct LaneShape {
+  static constexpr bool Q27 = L::Q == 27;
+  static constexpr int V2D = Q27 ? 2 : 4;
+  static constexpr int V2F = 4, EF = Q27 ? 4 : 2;
+  static constexpr int V2H = Q27 ? 4 : 8, EH = Q27 ? 4 : 8;
+};
+
+inline bool half_storage(int storage) {
+  return storage == LB_STORE_F16S || storage == LB_STORE_BF16S;
+}
+
 template <class L, int ORDER>
-inline const Impl* impl_for_storage(int storage) {
-  constexpr bool Q27 = L::Q == 27;
-  constexpr int V2D = Q27 ? 2 : 4;
-  // FP32: 2 x 2 nodes per lane (4 x 1 for D3Q27); 16-bit storage: one
-  // 16-byte chunk of 8 nodes (4 x 1 for D3Q27)
-  constexpr int V2F = 4, EF = Q27 ? 4 : 2;
-  constexpr int V2H = Q27 ? 4 : 8, EH = Q27 ? 4 : 8;
+inline const Impl* impl_wide(int storage) {
+  using LS = LaneShape<L>;
   switch (storage) {
-    case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, V2D, 2>::get();
-    case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, V2F, EF>::get();
-    case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, V2H, EH>::get();
-    case LB_STORE_BF16S: return ImplT<L, ORDER, __bf16, float, 4, V2H, EH>::get();
+    case LB_STORE_F64: return ImplT<L, ORDER, double, double, 2, LS::V2D, 2>::get();
+    case LB_STORE_F32: return ImplT<L, ORDER, float, float, 4, LS::V2F, LS::EF>::get();
   }
   return nullptr;
+}
+
+template <class L, int ORDER>
+inline const Impl* impl_half(int storage) {
+  using LS = LaneShape<L>;
+  switch (storage) {
+    case LB_STORE_F16S: return ImplT<L, ORDER, _Float16, float, 4, LS::V2H, LS::EH>::get();
+    case LB_STORE_BF16S: return ImplT<L, ORDER, __bf16, float, 4, LS::V2H, LS::EH>::get();
+  }
+  return nullptr;
+}
+
+template <class L, int ORDER>
+inline const Impl* impl_for_storage(int storage) {
+  return half_storage(storage) ? impl_half<L, ORDER>(storage) : impl_wide<L, ORDER>(storage);
 }
 
 // Two-species (colour-gradient) launchers: second-order Hermite terms only.
@@ -427,10 +452,14 @@ inline const Impl* impl2_for_storage(int storage) {
   return nullptr;
 }
 
-// One translation unit per lattice instantiates its kernels.
+// Translation units per lattice (and, for D3Q19 and D3Q27, per storage
+// width) instantiate the kernels.
 const Impl* impl_d2q9(int storage, int species);
 const Impl* impl_d3q19(int storage, int species);
+const Impl* impl_d3q19_half(int storage);
 const Impl* impl_d3q27(int order, int storage);
+const Impl* impl_d3q27_half(int storage);
 const Impl* impl_d3q27_order3(int storage);
+const Impl* impl_d3q27_order3_half(int storage);
 
 }  // namespace lbk

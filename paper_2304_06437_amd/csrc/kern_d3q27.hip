@@ -1,9 +1,11 @@
-// Kernel instantiations for D3Q27, second-order Hermite terms; the
-// third-order ones live in their own translation unit (compiled in parallel).
+// Kernel instantiations for D3Q27, second-order Hermite terms, 32/64-bit
+// storage; the 16-bit storage types and the third-order terms live in their
+// own translation units (compiled in parallel).
 #include "handle.hpp"
 
 namespace lbk {
 const Impl* impl_d3q27(int order, int storage) {
-  return order == 3 ? impl_d3q27_order3(storage) : impl_for_storage<D3Q27, 2>(storage);
+  if (order == 3) return impl_d3q27_order3(storage);
+  return half_storage(storage) ? impl_d3q27_half(storage) : impl_wide<D3Q27, 2>(storage);
 }
 }  // namespace lbk
